@@ -1,0 +1,175 @@
+/*
+ * perm_est.h -- C ABI of the MI355X sparse-permanent estimator.
+ *
+ * The library runs many independent sequential-importance-sampling
+ * trajectories of the generic adaptive estimator of "The Quick and the
+ * Dead: Estimating Sparse-Matrix Permanents with Adaptive Work Filtering"
+ * (Alg. 2; Alg. 1 with the row-order rule and no scaling) on one AMD
+ * Instinct MI355X (gfx950) and returns the estimate of per(A), Eq. (per1),
+ * together with the per-trajectory log-weights and the statistics of
+ * Sec. 2 and Sec. 4 "Metrics".
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status: PE_OK (0) or a negative PE_E*
+ *     code; none throws or aborts.  perm_est_last_error() gives a message
+ *     for the most recent failure in the calling thread.
+ *   - Matrix input arrays are HOST pointers owned by the caller; they are
+ *     validated and copied to the device by perm_est_create and may be
+ *     freed afterwards.
+ *   - Per-trajectory output arrays are DEVICE pointers (for example the
+ *     data_ptr() of torch tensors on the handle's device) owned by the
+ *     caller; any of them may be NULL.  The result struct is a host pointer.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it and the call returns after the stream has finished
+ *     the work it enqueued, so outputs are ready on return.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Results are a pure function of (matrix, schedule, seed, trajectory
+ *     index): trajectory k always draws its random numbers from
+ *     Philox4x32-10 with key = seed and counter = (k, b, t, d) where b is
+ *     the matrix index (0 for a single matrix), t the step and d the draw.
+ *   - "No perfect matching" is not an error: the run returns PE_OK with
+ *     p_match = 0, log_estimate = -inf and every trajectory dead.
+ */
+#ifndef PERM_EST_H
+#define PERM_EST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PE_OK 0
+#define PE_EINVAL (-1)   /* bad argument: n <= 0, index out of range,
+                            unsorted or duplicate entries, CSR/CSC mismatch,
+                            non-positive value, unknown preset, bad schedule */
+#define PE_ENOMEM (-2)   /* device or host allocation failed               */
+#define PE_EDEVICE (-3)  /* a HIP call failed (message has the HIP error)  */
+#define PE_ENOTSUP (-4)  /* valid request this build does not implement,
+                            e.g. a degree above 65534                        */
+
+/* vertex selection rule R_V (Alg. 2 input; Sec. 3.2) */
+#define PE_VR_MD 0        /* two-sided minimum degree over rows and columns,
+                             ties to the smallest vertex id (rows 0..n-1
+                             before columns n..2n-1)                        */
+#define PE_VR_ROW_ORDER 1 /* rows in index order (Alg. 1)                   */
+
+/* scaling policy P_SK (Sec. 3.3) */
+#define PE_SK_NONE 0      /* outer scaling only (or none if K0 = 0)         */
+#define PE_SK_FIXED 1     /* K full SK iterations on every child            */
+#define PE_SK_ADAPTIVE 2  /* ceil((1 - z) K) full iterations, clamped [0,K] */
+#define PE_SK_LOCAL 3     /* one local Jacobi repair per step, Eq. (local)  */
+
+/* support-filtering policy P_DM (Sec. 3.3) */
+#define PE_DM_NONE 0
+#define PE_DM_ALL 1       /* DM on every child                              */
+#define PE_DM_THRS 2      /* DM when z < theta_th                           */
+#define PE_DM_TRCK 3      /* track *= z; DM when track < theta_tr, then 1   */
+
+typedef struct perm_est perm_est_t; /* opaque; owns all device state */
+
+/* option flags */
+#define PE_FLAG_FORCE_HBM 1u  /* keep per-trajectory state in HBM scratch even
+                                 when it would fit in LDS (results are
+                                 identical; used to cross-check the tiers) */
+
+typedef struct {
+    int32_t device;  /* HIP device ordinal                                 */
+    uint32_t flags;  /* PE_FLAG_* bits; other bits must be 0               */
+} perm_est_options;
+
+/* Inputs of Alg. 2: R_V, K0, K, P_SK, P_DM and the two thresholds, plus
+ * whether the shared initial DM filter (Alg. 2 preprocessing) runs. */
+typedef struct {
+    int32_t vertex_rule;  /* PE_VR_*                                        */
+    int32_t sk_policy;    /* PE_SK_*                                        */
+    int32_t dm_policy;    /* PE_DM_*                                        */
+    int32_t initial_dm;   /* 1 = filter unsupported entries once, shared    */
+    int32_t K0;           /* outer SK iterations (>= 0)                     */
+    int32_t K;            /* inner SK cap (>= 0)                            */
+    double theta_th;      /* Thrs threshold                                 */
+    double theta_tr;      /* Trck threshold                                 */
+    int32_t reserved[4];  /* must be 0                                      */
+} perm_est_schedule;
+
+typedef struct {
+    double log_estimate;  /* ln of the sample mean of X; -inf if none alive */
+    double p_match;       /* fraction of trajectories with X > 0            */
+    double rel_spread;    /* sd(X) (M-1 denominator) / |mean|, zeros incl.  */
+    double rse;           /* rel_spread / sqrt(M)                           */
+    double ess;           /* (sum X)^2 / sum X^2                            */
+    double var_logw;      /* sample variance of ln X over the survivors     */
+    double max_logw;      /* largest ln X                                   */
+    int64_t n_traj;       /* M                                              */
+    int64_t n_alive;
+    int64_t n_dm;         /* inner DM calls, summed over trajectories       */
+    int64_t n_full_sk;    /* full SK iterations, summed                     */
+    int64_t n_local_sk;   /* local repairs, summed                          */
+    int64_t n_steps;      /* completed matching steps, summed               */
+    double seconds;       /* wall time of the trajectory + reduction work   */
+} perm_est_result;
+
+/* Create a handle for one n x n matrix A given in both CSR and CSC form
+ * (Sec. 2, "Support filtering": rows and columns are the two vertex sides
+ * of the bipartite graph G_A).
+ *   row_ptr[n+1], col_idx[nnz]: CSR, column indices ascending and unique
+ *                               within each row;
+ *   col_ptr[n+1], row_idx[nnz]: CSC of the same entries, row indices
+ *                               ascending within each column;
+ *   values[nnz]: entry values in CSR order, all > 0, or NULL for a 0/1
+ *                matrix.
+ * All arrays are host memory; int32 indices (nnz < 2^31).
+ * Errors: PE_EINVAL (inconsistent or out-of-range input), PE_ENOTSUP
+ * (a row or column with more than 65534 entries), PE_ENOMEM, PE_EDEVICE. */
+int perm_est_create(int32_t n, int64_t nnz,
+                    const int32_t *row_ptr, const int32_t *col_idx,
+                    const int32_t *col_ptr, const int32_t *row_idx,
+                    const float *values, const perm_est_options *opts,
+                    perm_est_t **out);
+
+/* Fill *out with a named schedule: the five variants of Sec. 4 --
+ * "fixed_all", "adaptive_threshold", "local_threshold", "adaptive_tracked",
+ * "local_tracked" (two-sided MD, K0 = 100, K = 10, theta = 0.33, shared
+ * initial DM) -- and "plain" (Alg. 2 with MD, no scaling, no filtering),
+ * "rasmussen" (Alg. 1), "local_nodm" (local_threshold without inner DM).
+ * Errors: PE_EINVAL for an unknown name. */
+int perm_est_schedule_preset(const char *name, perm_est_schedule *out);
+
+/* Run trajectories 0..n_traj-1 and reduce them (Alg. 2 per trajectory;
+ * statistics of Sec. 2 and Sec. 4 "Metrics").
+ *   res:       host, required; statistics over the n_traj trajectories.
+ *   logw:      device double[n_traj], ln X (-inf when X = 0), or NULL.
+ *   alive:     device uint8[n_traj], 1 iff X > 0, or NULL.
+ *   path_hash: device uint64[n_traj], SplitMix64 fold of (v_t, u_t), 0 for
+ *              dead trajectories, or NULL.
+ * Errors: PE_EINVAL (n_traj < 1 or >= 2^32, bad schedule), PE_ENOTSUP
+ * (schedule this build cannot run for this n), PE_ENOMEM, PE_EDEVICE. */
+int perm_est_run(perm_est_t *h, int64_t n_traj, uint64_t seed,
+                 const perm_est_schedule *sched, perm_est_result *res,
+                 double *logw, uint8_t *alive, uint64_t *path_hash,
+                 void *stream);
+
+/* As perm_est_run for trajectories first..first+count-1 (for resuming or
+ * sharding; results are identical to the same ids inside a larger run).
+ * Outputs are indexed 0..count-1.  Additional optional device outputs:
+ *   path:     int32[count][2n]: (v_t, u_t) vertex ids per completed step,
+ *             rows 0..n-1, columns n..2n-1; -1 after the last step.
+ *   counters: int32[count][4]: completed steps, inner DM calls, full SK
+ *             iterations, local repairs. */
+int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count,
+                       uint64_t seed, const perm_est_schedule *sched,
+                       perm_est_result *res, double *logw, uint8_t *alive,
+                       uint64_t *path_hash, int32_t *path, int32_t *counters,
+                       void *stream);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+void perm_est_destroy(perm_est_t *h);
+
+/* Message of the last failed call in this thread ("" if none). */
+const char *perm_est_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PERM_EST_H */

@@ -143,6 +143,8 @@ def preset(name: str) -> Schedule:
         "local_threshold": Schedule(sk_policy=SK_LOCAL, dm_policy=DM_THRS, **both),
         "adaptive_tracked": Schedule(sk_policy=SK_ADAPTIVE, dm_policy=DM_TRCK, **both),
         "local_tracked": Schedule(sk_policy=SK_LOCAL, dm_policy=DM_TRCK, **both),
+        # local repair every step, no inner filtering (large-n workload)
+        "local_nodm": Schedule(sk_policy=SK_LOCAL, dm_policy=DM_NONE, **both),
     }
     if name not in table:
         raise KeyError(name)

@@ -27,7 +27,8 @@
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  *   - MD tie-break: the active vertex of minimum current degree with the
- *     smallest id; rows are ids 0..n-1, columns n..2n-1.
+ *     smallest id; rows are ids 0..n-1, columns n..2n-1 (found with a
+ *     binary heap of (degree, id) keys, lazily discarding stale keys).
  *   - a trajectory is dead as soon as some active vertex of the child has
  *     degree 0 (for the MD rule this is exactly the next step's dead end;
  *     in every case X = 0 as Alg. 2 would return).
@@ -489,8 +490,70 @@ typedef struct {
     uint8_t *mark_r, *mark_c;
     int32_t *list_r, *list_c;
     double *new_r, *new_c;
+    uint64_t *heap;    /* binary min-heap of (degree << 32 | vertex) keys  */
+    int64_t heap_n, heap_cap;
     dm_work dm;
 } traj_work;
+
+/* ---- binary min-heap with lazy deletion: the minimum-degree rule is
+ * "smallest (degree, id) among active vertices"; every degree change
+ * pushes the new key and stale keys are discarded when they surface. */
+static int heap_push(traj_work *w, uint64_t key)
+{
+    if (w->heap_n == w->heap_cap) {
+        int64_t cap = w->heap_cap ? 2 * w->heap_cap : 1024;
+        uint64_t *h = realloc(w->heap, sizeof(uint64_t) * (size_t)cap);
+        if (!h) return -1;
+        w->heap = h; w->heap_cap = cap;
+    }
+    int64_t i = w->heap_n++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (w->heap[p] <= key) break;
+        w->heap[i] = w->heap[p];
+        i = p;
+    }
+    w->heap[i] = key;
+    return 0;
+}
+
+static void heap_pop(traj_work *w)
+{
+    uint64_t last = w->heap[--w->heap_n];
+    int64_t i = 0, N = w->heap_n;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        uint64_t best = last;
+        if (l < N && w->heap[l] < best) { m = l; best = w->heap[l]; }
+        if (r < N && w->heap[r] < best) { m = r; }
+        if (m == i) break;
+        w->heap[i] = w->heap[m];
+        i = m;
+    }
+    if (N > 0) w->heap[i] = last;
+}
+
+static inline uint64_t heap_key(int32_t deg, int32_t x) { return ((uint64_t)(uint32_t)deg << 32) | (uint32_t)x; }
+
+/* smallest (degree, id) over the active vertices; -1 if none */
+static int32_t heap_min(traj_work *w, int32_t *deg_out)
+{
+    while (w->heap_n > 0) {
+        uint64_t k = w->heap[0];
+        int32_t x = (int32_t)(uint32_t)k, d = (int32_t)(k >> 32);
+        if (w->act[x] && w->deg[x] == d) { *deg_out = d; return x; }
+        heap_pop(w);
+    }
+    return -1;
+}
+
+static int heap_reset(const or_mat *A, traj_work *w)
+{
+    w->heap_n = 0;
+    for (int32_t x = 0; x < 2 * A->n; ++x)
+        if (w->act[x] && heap_push(w, heap_key(w->deg[x], x))) return -1;
+    return 0;
+}
 
 static int tw_alloc(traj_work *w, const or_mat *A)
 {
@@ -527,6 +590,7 @@ static void tw_free(traj_work *w)
     free(w->cand_v); free(w->cand_e); free(w->cand_w); free(w->cand_s);
     free(w->nb_v); free(w->nb_u); free(w->mark_r); free(w->mark_c);
     free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c);
+    free(w->heap);
     dm_free(&w->dm);
 }
 
@@ -708,6 +772,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
     memcpy(w->removed, removed0, (size_t)A->m);
     for (int32_t i = 0; i < n; ++i) { w->r[i] = r0[i]; w->c[i] = c0[i]; }
     recount_degrees(A, w);
+    if (heap_reset(A, w)) return;
 
     double mant = 1.0;
     int64_t ex = 0;
@@ -720,9 +785,8 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         if (S->vertex_rule == VR_ROW) {
             for (int32_t i = 0; i < n; ++i) if (w->act[i]) { v = i; break; }
         } else {
-            int32_t best = INT32_MAX;
-            for (int32_t x = 0; x < 2 * n; ++x)
-                if (w->act[x] && w->deg[x] < best) { best = w->deg[x]; v = x; }
+            int32_t dmin;
+            v = heap_min(w, &dmin);
         }
         /* ---- candidates N_t(v) */
         int32_t kc = residual_neighbours(A, w, v, w->cand_v, w->cand_e);
@@ -830,8 +894,16 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
 
         /* ---- B^{(t+1)} = B^{(t)} \ {v,u}; degree bookkeeping */
         w->act[v] = 0; w->act[u] = 0;
-        for (int32_t a = 0; a < k_rho; ++a) w->deg[w->nb_v[a]] -= 1;
-        for (int32_t a = 0; a < k_gam; ++a) w->deg[w->nb_u[a]] -= 1;
+        for (int32_t a = 0; a < k_rho; ++a) {
+            int32_t y = w->nb_v[a];
+            w->deg[y] -= 1;
+            if (heap_push(w, heap_key(w->deg[y], y))) return;
+        }
+        for (int32_t a = 0; a < k_gam; ++a) {
+            int32_t y = w->nb_u[a];
+            w->deg[y] -= 1;
+            if (heap_push(w, heap_key(w->deg[y], y))) return;
+        }
         out->steps = t + 1;
         track = track * z;
 
@@ -839,9 +911,8 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
 
         /* child dead end: some active vertex has no residual neighbour */
         {
-            int zero = 0;
-            for (int32_t x = 0; x < 2 * n; ++x) if (w->act[x] && w->deg[x] == 0) { zero = 1; break; }
-            if (zero) return;
+            int32_t dmin = -1;
+            if (heap_min(w, &dmin) < 0 || dmin == 0) return;
         }
 
         /* ---- DM policy */
@@ -856,6 +927,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
             if (events) events[2 * t] = 1;
             if (!ok) return;
             recount_degrees(A, w);
+            if (heap_reset(A, w)) return;
             track = 1.0;
         }
 

@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in ``include/perm_est.h``.
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  Loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpermest.so")
+
+PE_OK, PE_EINVAL, PE_ENOMEM, PE_EDEVICE, PE_ENOTSUP = 0, -1, -2, -3, -4
+
+
+class Options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [
+        ("vertex_rule", C.c_int32),
+        ("sk_policy", C.c_int32),
+        ("dm_policy", C.c_int32),
+        ("initial_dm", C.c_int32),
+        ("K0", C.c_int32),
+        ("K", C.c_int32),
+        ("theta_th", C.c_double),
+        ("theta_tr", C.c_double),
+        ("reserved", C.c_int32 * 4),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("log_estimate", C.c_double),
+        ("p_match", C.c_double),
+        ("rel_spread", C.c_double),
+        ("rse", C.c_double),
+        ("ess", C.c_double),
+        ("var_logw", C.c_double),
+        ("max_logw", C.c_double),
+        ("n_traj", C.c_int64),
+        ("n_alive", C.c_int64),
+        ("n_dm", C.c_int64),
+        ("n_full_sk", C.c_int64),
+        ("n_local_sk", C.c_int64),
+        ("n_steps", C.c_int64),
+        ("seconds", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = [
+    "perm_est_create",
+    "perm_est_schedule_preset",
+    "perm_est_run",
+    "perm_est_run_range",
+    "perm_est_destroy",
+    "perm_est_last_error",
+]
+
+_lib = None
+
+
+def load():
+    """Load libpermest.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library {LIB_PATH} is not built; run `python -m paper_2608_15390_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.perm_est_create.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P, C.POINTER(Options), C.POINTER(P)]
+    L.perm_est_create.restype = C.c_int
+    L.perm_est_schedule_preset.argtypes = [C.c_char_p, C.POINTER(Schedule)]
+    L.perm_est_schedule_preset.restype = C.c_int
+    L.perm_est_run.argtypes = [P, C.c_int64, C.c_uint64, C.POINTER(Schedule), C.POINTER(Result), P, P, P, P]
+    L.perm_est_run.restype = C.c_int
+    L.perm_est_run_range.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, C.POINTER(Schedule),
+                                     C.POINTER(Result), P, P, P, P, P, P]
+    L.perm_est_run_range.restype = C.c_int
+    L.perm_est_destroy.argtypes = [P]
+    L.perm_est_destroy.restype = None
+    L.perm_est_last_error.argtypes = []
+    L.perm_est_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+class PermEstError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"perm_est error {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int):
+    if rc != PE_OK:
+        raise PermEstError(rc, load().perm_est_last_error().decode(errors="replace"))

@@ -1,0 +1,124 @@
+// device.hpp -- wave64 primitives and the counter-based random numbers used
+// by every gfx950 kernel of the estimator.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pe {
+
+constexpr int kWave = 64;
+constexpr uint16_t kRetired = 0xFFFF;   // degree sentinel of a matched vertex
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Order this wave's earlier LDS / global accesses before its later ones
+// (values are exchanged between lanes of one wave through memory).
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = __shfl_xor(x, o);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float wave_max_f32(float x) {
+    // plain comparisons (no fmaxf) so NaNs never win, as in a sequential max
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        float y = __shfl_xor(x, o);
+        x = (y > x) ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// inclusive prefix sum over the 64 lanes in lane order
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint64_t y = __shfl_up(x, o);
+        if (l >= o) x += y;
+    }
+    return x;
+}
+
+// number of set bits of `mask` strictly below this lane
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+    const int l = lane_id();
+    uint64_t below = (l == 0) ? 0ull : (mask & (~0ull >> (64 - l)));
+    return __popcll(below);
+}
+
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int src) { return __shfl(v, src); }
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products, key bumped by the golden-ratio Weyl constants.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 64 random bits for (seed; trajectory k, matrix b, step t, draw d)
+__device__ __forceinline__ uint64_t rand64(uint64_t seed, uint32_t k, uint32_t b, uint32_t t, uint32_t d) {
+    U4 o = philox4x32_10(U4{k, b, t, d}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return ((uint64_t)o.y << 32) | o.x;
+}
+
+// Uniform integer in [0, W), W >= 1, by Lemire's multiply-and-reject method
+// (ACM TOMACS 2019); each rejection moves to the next draw index.
+__device__ __forceinline__ uint64_t uniform_below(uint64_t seed, uint32_t k, uint32_t b, uint32_t t,
+                                                  uint32_t d, uint64_t W) {
+    for (;;) {
+        const uint64_t x = rand64(seed, k, b, t, d);
+        const uint64_t hi = __umul64hi(x, W);
+        const uint64_t lo = x * W;
+        if (lo < W) {
+            const uint64_t thr = (0ull - W) % W;
+            if (lo < thr) { ++d; continue; }
+        }
+        return hi;
+    }
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014) folded over a word
+__device__ __forceinline__ uint64_t splitmix_fold(uint64_t h, uint64_t x) {
+    uint64_t z = h + 0x9E3779B97F4A7C15ull + x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace pe

@@ -1,0 +1,117 @@
+// reduce.hpp -- FP64 reduction of the trajectory log-weights into the
+// statistics of Sec. 2 and Sec. 4 "Metrics" (zeros included), in log space
+// so that per(A) beyond the FP64 range is representable.
+//   L  = max ln X over survivors, S1 = sum e^{lnX - L}, S2 = sum e^{2(lnX-L)}
+//   ln mean = L + ln S1 - ln M; CV^2 = M (M S2 / S1^2 - 1) / (M - 1);
+//   RSE = CV / sqrt(M); ESS = S1^2 / S2; p_match = n_alive / M.
+// One block per segment (matrix); each thread owns a strided subset and
+// the block combines partials in a fixed tree order, so results do not
+// depend on scheduling.
+#pragma once
+#include "device.hpp"
+
+namespace pe {
+
+struct DevStats {
+    double log_estimate, p_match, rel_spread, rse, ess, var_logw, max_logw;
+    int64_t n_traj, n_alive, n_dm, n_full_sk, n_local_sk, n_steps;
+};
+
+// compensated accumulation (Neumaier)
+struct KSum {
+    double s = 0.0, c = 0.0;
+    __device__ void add(double x) {
+        const double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+        s = t;
+    }
+    __device__ double value() const { return s + c; }
+};
+
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T *buf, Op op) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (t < o) buf[t] = op(buf[t], buf[t + o]);
+        __syncthreads();
+    }
+    const T r = buf[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(1024) k_reduce_stats(const double *logw, const uint8_t *alive,
+                                                      const int32_t *counters, const int64_t *seg_off,
+                                                      DevStats *out) {
+    __shared__ double dbuf[1024];
+    __shared__ long long ibuf[1024];
+    const int64_t lo = seg_off[blockIdx.x], hi = seg_off[blockIdx.x + 1];
+    const int t = threadIdx.x, B = blockDim.x;
+    auto dmax = [](double a, double b) { return a > b ? a : b; };
+    auto dadd = [](double a, double b) { return a + b; };
+    auto iadd = [](long long a, long long b) { return a + b; };
+
+    double L = -__builtin_huge_val();
+    long long na = 0, c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    for (int64_t q = lo + t; q < hi; q += B) {
+        if (alive[q]) { ++na; L = logw[q] > L ? logw[q] : L; }
+        if (counters) {
+            c0 += counters[4 * q + 0]; c1 += counters[4 * q + 1];
+            c2 += counters[4 * q + 2]; c3 += counters[4 * q + 3];
+        }
+    }
+    L = block_reduce(L, dbuf, dmax);
+    na = block_reduce(na, ibuf, iadd);
+    c0 = block_reduce(c0, ibuf, iadd);
+    c1 = block_reduce(c1, ibuf, iadd);
+    c2 = block_reduce(c2, ibuf, iadd);
+    c3 = block_reduce(c3, ibuf, iadd);
+
+    KSum s1, s2, m1;
+    for (int64_t q = lo + t; q < hi; q += B) {
+        if (!alive[q]) continue;
+        const double a = exp(logw[q] - L);
+        s1.add(a);
+        s2.add(a * a);
+        m1.add(logw[q]);
+    }
+    const double S1 = block_reduce(s1.value(), dbuf, dadd);
+    const double S2 = block_reduce(s2.value(), dbuf, dadd);
+    const double M1 = block_reduce(m1.value(), dbuf, dadd);
+    const double mean = na > 0 ? M1 / (double)na : 0.0;
+    KSum vv;
+    for (int64_t q = lo + t; q < hi; q += B) {
+        if (!alive[q]) continue;
+        const double d = logw[q] - mean;
+        vv.add(d * d);
+    }
+    const double V = block_reduce(vv.value(), dbuf, dadd);
+
+    if (t == 0) {
+        DevStats r;
+        const double M = (double)(hi - lo);
+        r.n_traj = hi - lo;
+        r.n_alive = na;
+        r.n_steps = c0; r.n_dm = c1; r.n_full_sk = c2; r.n_local_sk = c3;
+        r.max_logw = L;
+        r.p_match = M > 0 ? (double)na / M : __builtin_nan("");
+        if (na == 0) {
+            r.log_estimate = -__builtin_huge_val();
+            r.rel_spread = r.rse = r.var_logw = __builtin_nan("");
+            r.ess = 0.0;
+        } else {
+            r.log_estimate = L + log(S1) - log(M);
+            double cv2 = M > 1 ? M * (M * S2 / (S1 * S1) - 1.0) / (M - 1.0) : __builtin_nan("");
+            if (cv2 < 0) cv2 = 0;
+            r.rel_spread = sqrt(cv2);
+            r.rse = r.rel_spread / sqrt(M);
+            r.ess = S1 * S1 / S2;
+            r.var_logw = na > 1 ? V / (double)(na - 1) : 0.0;
+        }
+        out[blockIdx.x] = r;
+    }
+}
+
+}  // namespace pe

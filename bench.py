@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X sparse-permanent estimator.
+
+One "step" is one pass of the whole hot path over one batch: the persistent
+trajectory kernel over n_traj trajectories of the large sparse workload
+(n = 1e5, planted random permutation plus 7n uniform extra entries, avg
+degree 8) with the plain scaled schedule (shared initial filter, 100 outer
+SK iterations, one local repair per step), followed by the FP64 reduction.
+The metric is effective samples per second, ESS / T with
+ESS = (sum X)^2 / sum X^2 over the batch and T the wall time of the step.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported: this build
+runs on one GPU (see the design notes for how the work would shard).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective samples/sec at equal relative error, learned vs plain, n=1e5 avg deg 8"
+HBM_PEAK_GBS = 8000.0
+
+KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/csrc/device.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(res: dict, n: int, n_leaf: int, scaled: bool, local: bool) -> float:
+    """Bytes the trajectory kernel must move per launch for this data layout,
+    from the work counters (per-unit figures are listed in the design notes):
+      selection: 256 u16 leaves of one group (512 B) + 2 list pointers (16 B)
+      scanned entry at v or u: 4 B index + 2 B neighbour degree (+4 B scale
+        for the scaled proposal, charged on every scanned entry)
+      decrement: 2 B read + 2 B write; retiring v and u: 2 x 2 B
+      local-repair entry: 4 B index + 2 B degree + 4 B scale or stamp
+      local value: 8 B list pointers + 4 B old value + 4 B new value
+      trajectory init: degree template read + write (4 B per leaf),
+        r/c copy (16 B per row/column pair), stamp clear (8 B per row/column)
+    """
+    steps = res["n_steps"]
+    b = steps * (512 + 16 + 4)
+    b += res["n_entries_scanned"] * (10 if scaled else 6)
+    b += res["n_decrements"] * 4
+    b += res["n_local_entries"] * 10
+    b += res["n_local_values"] * 16
+    per_traj = 4 * n_leaf + (16 * n if scaled else 0) + (8 * n if local else 0)
+    b += res["n_traj"] * per_traj
+    return float(b)
+
+
+def load_traffic(workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, or None
+    when the kernel sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--schedule", default="local_nodm")
+    ap.add_argument("--n-traj", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU; N > 1 is not supported "
+              "(trajectories shard trivially by id, see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+
+    if args.workload == "large":
+        M = G.config_large(1)
+        n_traj = args.n_traj or 100_000
+        wname = "large_n1e5_deg8"
+    else:
+        M = G.config_small(1)
+        n_traj = args.n_traj or 10_000
+        wname = "small_n20"
+    sched = P.preset(args.schedule)
+    scaled = sched.K0 > 0 or sched.sk_policy != 0
+    local = sched.sk_policy == 3
+    dev = torch.device("cuda", 0)
+    est = P.PermEst(M, device=0)
+    # untimed set-up: preprocessing (initial filter, outer SK, templates)
+    est.run(0, 64, args.seed, sched, want_logw=False, want_alive=False)
+    torch.cuda.synchronize()
+
+    results = []
+    first_logw = None
+    for w in range(args.warmup):
+        est.run((w + 1) * n_traj * 16, n_traj, args.seed, sched, want_logw=False, want_alive=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = est.run(k * n_traj, n_traj, args.seed, sched, want_logw=(k == 0), want_alive=(k == 0))
+        results.append(out["result"])
+        if k == 0:
+            first_logw = (out["logw"], out["alive"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ess = sum(r["ess"] for r in results)
+    value = ess / (t1 - t0)
+    kern_s = sum(r["seconds"] for r in results) / len(results)
+    n_leaf = (2 * M.n + 255) // 256 * 256
+    abytes = sum(algorithmic_bytes(r, M.n, n_leaf, scaled, local) for r in results) / len(results)
+    achieved = abytes / kern_s / 1e9
+    traffic = load_traffic(wname)
+    r0 = results[0]
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "effective samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 weights, f32 scaling",
+        "data": "synthetic (seeded generator)",
+        "config": {
+            "workload": wname, "n": M.n, "nnz": M.nnz, "n_traj": n_traj,
+            "schedule": args.schedule, "method": "plain scaled (no learned proposal)",
+            "parallelism": "1 GPU",
+        },
+        "estimate": {
+            "log_estimate": r0["log_estimate"], "p_match": r0["p_match"], "rel_spread": r0["rel_spread"],
+            "rse": r0["rse"], "ess": r0["ess"], "var_logw": r0["var_logw"],
+            "traj_per_s": n_traj / (ms_per_step / 1e3), "steps_per_traj": r0["n_steps"] / n_traj,
+            "n_local_sk": r0["n_local_sk"],
+        },
+        "roofline": {
+            "kernel": "pe::traj_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": abytes,
+            "kernel_ms": kern_s * 1e3,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        A = O.OMatrix(M)
+        osched = O.preset(args.schedule)
+        pre = O.prep(A, osched)
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        # bounded sample: first ids of the timed batch, grown until ~cpu_seconds
+        count, elapsed = threads, 0.0
+        while True:
+            t = time.perf_counter()
+            o = O.run(A, osched, seed=args.seed, first=0, count=count, nthreads=threads, pre=pre)
+            elapsed = time.perf_counter() - t
+            if elapsed >= args.cpu_seconds / 4 or count >= n_traj:
+                break
+            count = min(n_traj, int(count * max(2.0, args.cpu_seconds / max(elapsed, 1e-3) / 2)))
+        rate = count / elapsed
+        lw, al = first_logw
+        lw = lw[:count].cpu().numpy()
+        al = al[:count].cpu().numpy()
+        same = bool(np.array_equal(al, o["alive"]) and
+                    np.allclose(lw[al == 1], o["logw"][al == 1], rtol=1e-12, atol=0))
+        line["cpu_baseline"] = {
+            "value": r0["ess"] * rate / n_traj,
+            "unit": "effective samples/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"trajectory ids 0..{count - 1} of the timed batch ({count} of {n_traj}), "
+                      f"{elapsed:.1f} s on {threads} threads; ESS/s = batch ESS x oracle traj/s / n_traj",
+            "traj_per_s": rate,
+            "matches_gpu": same,
+        }
+    print(json.dumps(line), flush=True)
+    est.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -108,6 +108,11 @@ typedef struct {
     int64_t n_local_sk;   /* local repairs, summed                          */
     int64_t n_steps;      /* completed matching steps, summed               */
     double seconds;       /* wall time of the trajectory + reduction work   */
+    /* work units, summed over trajectories (drive the byte model) */
+    int64_t n_entries_scanned; /* adjacency entries read at v and u         */
+    int64_t n_decrements;      /* residual-degree decrements                */
+    int64_t n_local_entries;   /* entries gathered or summed by local repair */
+    int64_t n_local_values;    /* scaling values recomputed by local repair */
 } perm_est_result;
 
 /* Create a handle for one n x n matrix A given in both CSR and CSC form

@@ -50,6 +50,10 @@ class Result(C.Structure):
         ("n_local_sk", C.c_int64),
         ("n_steps", C.c_int64),
         ("seconds", C.c_double),
+        ("n_entries_scanned", C.c_int64),
+        ("n_decrements", C.c_int64),
+        ("n_local_entries", C.c_int64),
+        ("n_local_values", C.c_int64),
     ]
 
     def as_dict(self):

@@ -62,9 +62,10 @@ struct Prepared {
     int64_t m = 0;
     int32_t dmax = 0;
     int32_t *row_ptr = nullptr, *col_idx = nullptr, *col_ptr = nullptr, *row_idx = nullptr,
-            *csc2csr = nullptr;
+            *csc2csr = nullptr, *edge_row = nullptr;
     float *val = nullptr, *val_csc = nullptr;
     float *r0 = nullptr, *c0 = nullptr;
+    int32_t *mate_r = nullptr, *mate_c = nullptr;  // perfect matching found by the initial filter
     uint16_t *deg0 = nullptr;
     uint32_t *tree0 = nullptr;
     int32_t n_leaf = 0;
@@ -73,9 +74,9 @@ struct Prepared {
     void release() {
         if (own) {
             dfree(row_ptr); dfree(col_idx); dfree(col_ptr); dfree(row_idx); dfree(csc2csr);
-            dfree(val); dfree(val_csc);
+            dfree(val); dfree(val_csc); dfree(edge_row);
         }
-        dfree(r0); dfree(c0); dfree(deg0); dfree(tree0);
+        dfree(r0); dfree(c0); dfree(deg0); dfree(tree0); dfree(mate_r); dfree(mate_c);
     }
 };
 
@@ -89,7 +90,7 @@ struct perm_est {
     bool weighted = false;
     int32_t dmax = 0;
     int32_t *row_ptr = nullptr, *col_idx = nullptr, *col_ptr = nullptr, *row_idx = nullptr,
-            *csc2csr = nullptr;
+            *csc2csr = nullptr, *edge_row = nullptr;
     float *val = nullptr, *val_csc = nullptr;
     std::vector<Prepared> preps;
     int cu_count = 256;
@@ -97,6 +98,7 @@ struct perm_est {
     char *hbm_state = nullptr;
     size_t hbm_bytes = 0;
     uint32_t *work = nullptr;
+    unsigned long long *work_totals = nullptr;
     DevStats *stats = nullptr;
     int64_t *seg = nullptr;
     int32_t *flags = nullptr;  // small scratch integers for preprocessing loops
@@ -142,7 +144,8 @@ int zero_flag(int32_t *dflag, hipStream_t s) {
 // rounds plus multi-source BFS augmentation, strongly connected components
 // of the contracted alternating digraph by trimming and max-label colouring,
 // then keep[e].  Returns ok = 0 when no perfect matching exists.
-int initial_filter(perm_est *h, uint8_t *keep, int32_t *ok, hipStream_t s) {
+int initial_filter(perm_est *h, uint8_t *keep, int32_t *ok, int32_t *out_mate_r, int32_t *out_mate_c,
+                   hipStream_t s) {
     const int32_t n = h->n;
     int32_t *mate_r, *mate_c, *root, *level, *claim, *path_end, *scc, *color, *mark;
     int rc;
@@ -218,6 +221,8 @@ int initial_filter(perm_est *h, uint8_t *keep, int32_t *ok, hipStream_t s) {
         }
         k_keep_edges<<<gb, 256, 0, s>>>(n, h->row_ptr, h->col_idx, mate_r, mate_c, scc, keep);
         PE_HIP(hipGetLastError());
+        PE_HIP(hipMemcpyAsync(out_mate_r, mate_r, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        PE_HIP(hipMemcpyAsync(out_mate_c, mate_c, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
         PE_HIP(hipStreamSynchronize(s));
         return PE_OK;
     };
@@ -236,12 +241,14 @@ int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, P
     P.m = h->m;
     P.row_ptr = h->row_ptr; P.col_idx = h->col_idx; P.col_ptr = h->col_ptr;
     P.row_idx = h->row_idx; P.csc2csr = h->csc2csr; P.val = h->val; P.val_csc = h->val_csc;
+    P.edge_row = h->edge_row;
     P.dmax = h->dmax;
     if (initial_dm && h->m > 0) {
         uint8_t *keep;
         if ((rc = dalloc(&keep, (size_t)h->m))) return rc;
         int32_t ok = 0;
-        rc = initial_filter(h, keep, &ok, s);
+        if ((rc = dalloc(&P.mate_r, n)) || (rc = dalloc(&P.mate_c, n))) { dfree(keep); return rc; }
+        rc = initial_filter(h, keep, &ok, P.mate_r, P.mate_c, s);
         if (rc) { dfree(keep); return rc; }
         P.ok = ok;
         if (ok) {
@@ -252,7 +259,7 @@ int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, P
                 return rc;
             }
             P.own = true;
-            P.col_idx = P.row_idx = P.csc2csr = nullptr;
+            P.col_idx = P.row_idx = P.csc2csr = P.edge_row = nullptr;
             P.val = P.val_csc = nullptr;
             const unsigned gb = blocks_for(n);
             k_row_keep_count<<<gb, 256, 0, s>>>(n, h->row_ptr, keep, len);
@@ -262,7 +269,7 @@ int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, P
             PE_HIP(hipStreamSynchronize(s));
             P.m = m2;
             if ((rc = dalloc(&P.col_idx, m2)) || (rc = dalloc(&P.row_idx, m2)) ||
-                (rc = dalloc(&P.csc2csr, m2)))
+                (rc = dalloc(&P.csc2csr, m2)) || (rc = dalloc(&P.edge_row, m2)))
                 return rc;
             if (h->val && ((rc = dalloc(&P.val, m2)) || (rc = dalloc(&P.val_csc, m2)))) return rc;
             k_row_scatter<<<gb, 256, 0, s>>>(n, h->row_ptr, h->col_idx, h->val, keep, P.row_ptr,
@@ -272,6 +279,7 @@ int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, P
             k_col_scatter<<<gb, 256, 0, s>>>(n, h->col_ptr, h->row_idx, h->csc2csr, keep, new_id,
                                              P.col_ptr, P.row_idx, P.csc2csr);
             if (h->val) k_gather_f32<<<blocks_for(m2), 256, 0, s>>>(m2, P.val, P.csc2csr, P.val_csc);
+            k_edge_row<<<gb, 256, 0, s>>>(n, P.row_ptr, P.edge_row);
             PE_HIP(hipGetLastError());
             // maximum degree of the filtered matrix
             std::vector<int32_t> rp(n + 1), cp(n + 1);
@@ -337,6 +345,29 @@ int get_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, Pre
 }
 
 uint32_t align_up(uint64_t x, uint64_t a) { return (uint32_t)((x + a - 1) / a * a); }
+
+template <int SK, bool DM>
+void launch_w(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s, const TrajArgs &a) {
+    if (wt) traj_kernel<SK, DM, true><<<blocks, threads, shmem, s>>>(a);
+    else traj_kernel<SK, DM, false><<<blocks, threads, shmem, s>>>(a);
+}
+
+template <int SK>
+void launch_dm(bool dm, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+               const TrajArgs &a) {
+    if (dm) launch_w<SK, true>(wt, blocks, threads, shmem, s, a);
+    else launch_w<SK, false>(wt, blocks, threads, shmem, s, a);
+}
+
+void launch_traj(int sk, bool dm, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+                 const TrajArgs &a) {
+    switch (sk) {
+        case PE_SK_NONE: launch_dm<kSkNone>(dm, wt, blocks, threads, shmem, s, a); break;
+        case PE_SK_FIXED: launch_dm<kSkFixed>(dm, wt, blocks, threads, shmem, s, a); break;
+        case PE_SK_ADAPTIVE: launch_dm<kSkAdaptive>(dm, wt, blocks, threads, shmem, s, a); break;
+        default: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, a); break;
+    }
+}
 
 int check_schedule(const perm_est_schedule *s) {
     if (!s) return fail(PE_EINVAL, "schedule is NULL");
@@ -423,7 +454,7 @@ int perm_est_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_
         h->cu_count = cus;
     if ((rc = dalloc(&h->row_ptr, n + 1)) || (rc = dalloc(&h->col_ptr, n + 1)) ||
         (rc = dalloc(&h->col_idx, nnz)) || (rc = dalloc(&h->row_idx, nnz)) ||
-        (rc = dalloc(&h->csc2csr, nnz)) || (rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->stats, 1)) ||
+        (rc = dalloc(&h->csc2csr, nnz)) || (rc = dalloc(&h->edge_row, nnz)) || (rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, 5)) || (rc = dalloc(&h->stats, 1)) ||
         (rc = dalloc(&h->seg, 2)) || (rc = dalloc(&h->flags, 8)))
         return bail(rc);
     if (values && ((rc = dalloc(&h->val, nnz)) || (rc = dalloc(&h->val_csc, nnz)))) return bail(rc);
@@ -439,6 +470,7 @@ int perm_est_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_
     int32_t err = 0;
     if (hipMemset(h->flags, 0, sizeof(int32_t)) != hipSuccess) return bail(fail(PE_EDEVICE, "hipMemset failed"));
     k_csc2csr<<<blocks_for(n), 256>>>(n, h->row_ptr, h->col_idx, h->col_ptr, h->row_idx, h->csc2csr, h->flags);
+    k_edge_row<<<blocks_for(n), 256>>>(n, h->row_ptr, h->edge_row);
     if (values) k_gather_f32<<<blocks_for(nnz), 256>>>(nnz, h->val, h->csc2csr, h->val_csc);
     if (hipGetLastError() != hipSuccess || hipMemcpy(&err, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return bail(fail(PE_EDEVICE, "edge map kernel failed"));
@@ -452,8 +484,8 @@ void perm_est_destroy(perm_est_t *h) {
     (void)hipSetDevice(h->device);
     for (auto &P : h->preps) P.release();
     dfree(h->row_ptr); dfree(h->col_idx); dfree(h->col_ptr); dfree(h->row_idx); dfree(h->csc2csr);
-    dfree(h->val); dfree(h->val_csc);
-    dfree(h->hbm_state); dfree(h->work); dfree(h->stats); dfree(h->seg); dfree(h->flags);
+    dfree(h->edge_row); dfree(h->val); dfree(h->val_csc);
+    dfree(h->hbm_state); dfree(h->work); dfree(h->work_totals); dfree(h->stats); dfree(h->seg); dfree(h->flags);
     dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -469,7 +501,6 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
         return fail(PE_EINVAL, "trajectory range must lie in [0, 2^32) and be non-empty");
     int rc;
     if ((rc = check_schedule(sched))) return rc;
-    if (sched->dm_policy != PE_DM_NONE) return fail(PE_ENOTSUP, "inner DM is not available in this build");
     PE_HIP(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     Prepared *P;
@@ -499,25 +530,28 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) { uint32_t at = align_up(o, 16); o = (uint64_t)at + bytes; return at; };
     L.deg = take((uint64_t)P->n_leaf * 2);
-    L.r = take(own_rc ? 4ull * n : 0);
-    L.c = take(own_rc ? 4ull * n : 0);
-    L.stamp = take(local ? 8ull * n : 0);
+    L.rec = take(own_rc ? 16ull * n : 0);
     L.lst_a = take(4ull * P->dmax);
     L.lst_b = take(4ull * P->dmax);
     L.loc_r = take(local ? 4ull * n : 0);
     L.loc_c = take(local ? 4ull * n : 0);
-    L.new_r = take(local ? 4ull * n : 0);
-    L.new_c = take(local ? 4ull * n : 0);
+    L.new_v = take(local ? 8ull * n : 0);
     L.rem = take(dm ? 4ull * ((P->m + 31) / 32) : 0);
-    L.dm = take(0);
+    L.mate_r = take(dm ? 4ull * n : 0);
+    L.mate_c = take(dm ? 4ull * n : 0);
+    L.ws = take(dm ? 24ull * n : 0);
     L.bytes = align_up(o, 256);
+    if (o >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
 
     TrajArgs a{};
-    a.A = DevMat{n, (int32_t)P->m, P->row_ptr, P->col_idx, P->col_ptr, P->row_idx, P->csc2csr, P->val, P->val_csc};
+    a.A = DevMat{n, (int32_t)P->m, P->row_ptr, P->col_idx, P->col_ptr, P->row_idx, P->csc2csr,
+                 P->edge_row, P->val, P->val_csc};
     a.r0 = P->r0;
     a.c0 = P->c0;
     a.deg0 = P->deg0;
     a.tree0 = P->tree0;
+    a.mate0_r = P->mate_r;
+    a.mate0_c = P->mate_c;
     a.n_leaf = P->n_leaf;
     a.tree = P->tree;
     a.st = L;
@@ -527,7 +561,6 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
     a.dm_policy = sched->dm_policy;
     a.K = sched->K;
     a.scaled = (P->r0 != nullptr) || own_rc;
-    a.own_rc = own_rc;
     a.theta_th = sched->theta_th;
     a.theta_tr = sched->theta_tr;
     a.seed = seed;
@@ -541,6 +574,7 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
     a.counters = cn;
     a.work_next = h->work;
     a.err = h->work + 1;
+    a.work_totals = h->work_totals;
 
     // ---- tier and launch shape
     const size_t tree_bytes = (size_t)P->tree.total * 4;
@@ -578,15 +612,18 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
     PE_HIP(hipMemcpyAsync(h->seg, seg_host, sizeof(seg_host), hipMemcpyHostToDevice, s));
     k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
     k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
+    k_fill_i32<<<1, 64, 0, s>>>(10, reinterpret_cast<int32_t *>(h->work_totals), 0);
     PE_HIP(hipEventRecord(h->ev0, s));
-    traj_kernel<<<blocks, wpb * kWave, shmem, s>>>(a);
+    launch_traj(sched->sk_policy, dm, P->val != nullptr, blocks, wpb * kWave, shmem, s, a);
     PE_HIP(hipGetLastError());
     k_reduce_stats<<<1, 1024, 0, s>>>(lw, al, cn, h->seg, h->stats);
     PE_HIP(hipGetLastError());
     PE_HIP(hipEventRecord(h->ev1, s));
     DevStats st;
     uint32_t err_bits = 0;
+    unsigned long long wt[5];
     PE_HIP(hipMemcpyAsync(&st, h->stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(wt, h->work_totals, sizeof(wt), hipMemcpyDeviceToHost, s));
     PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
     if (err_bits) return fail(PE_EDEVICE, "trajectory kernel reported an internal inconsistency (bits " +
@@ -607,6 +644,10 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
     res->n_local_sk = st.n_local_sk;
     res->n_steps = st.n_steps;
     res->seconds = ms * 1e-3;
+    res->n_entries_scanned = (int64_t)wt[0];
+    res->n_decrements = (int64_t)wt[1];
+    res->n_local_entries = (int64_t)wt[2];
+    res->n_local_values = (int64_t)wt[3];
     return PE_OK;
 }
 

@@ -25,6 +25,12 @@ __global__ void k_csc2csr(int32_t n, const int32_t *row_ptr, const int32_t *col_
     }
 }
 
+__global__ void k_edge_row(int32_t n, const int32_t *row_ptr, int32_t *edge_row) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) edge_row[e] = i;
+}
+
 __global__ void k_gather_f32(int64_t m, const float *src, const int32_t *idx, float *dst) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < m) dst[p] = src[idx[p]];

@@ -7,13 +7,16 @@
 //   deg    u16[n_leaf]  residual degree of every vertex (rows 0..n-1,
 //                       columns n..2n-1), 0xFFFF once matched; padded with
 //                       0xFFFF to a multiple of 256
-//   r, c   f32[n]       scaling vectors when a policy changes them
-//   stamp  i32[2n]      set-membership marks of the local repair
-//   lst_a  i32[dmax]    N_t(v): the candidates of the selected vertex
-//   lst_b  i32[dmax]    N_t(u) \ {v}
+//   rec    {f32,i32}[2n] per vertex: its scaling value (r_i for a row, c_j
+//                       for a column; negative once matched) and the stamp
+//                       of the local repair's set membership
+//   lst_a  i32[dmax]    N_t(v) for lists longer than a wave
+//   lst_b  i32[dmax]    N_t(u) \ {v} for lists longer than a wave
 //   loc_r, loc_c i32[n] R_loc, C_loc of Eq. (local)
-//   new_r, new_c f32[n] staged values of the Jacobi repair
+//   new_v  f32[2n]      staged values of a repair larger than one wave
 //   rem    u32[m/32]    edges removed by inner DM (CSR edge ids)
+//   mate_r, mate_c i32[n] perfect matching kept for inner DM
+//   ws     i32[6n]      inner-DM work space (BFS, Tarjan)
 // Minimum-degree selection uses a min-tree whose internal nodes are u32 in
 // LDS: level-1 node g is the minimum of leaves [256g, 256g+256), higher
 // levels have fan-out 64, the top level has at most 64 nodes.  The leftmost
@@ -27,8 +30,9 @@ namespace pe {
 struct DevMat {
     int32_t n, m;
     const int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *csc2csr;
-    const float *val;      // CSR order, nullptr = 0/1
-    const float *val_csc;  // CSC order, nullptr = 0/1
+    const int32_t *edge_row;  // row of every CSR edge
+    const float *val;         // CSR order, nullptr = 0/1
+    const float *val_csc;     // CSC order, nullptr = 0/1
 };
 
 struct TreeLayout {
@@ -39,8 +43,13 @@ struct TreeLayout {
 };
 
 struct StateLayout {  // byte offsets in one trajectory's state block
-    uint32_t deg, r, c, stamp, lst_a, lst_b, loc_r, loc_c, new_r, new_c, rem, dm;
+    uint32_t deg, rec, lst_a, lst_b, loc_r, loc_c, new_v, rem, mate_r, mate_c, ws;
     uint32_t bytes;
+};
+
+struct Rec {
+    float s;        // scaling value; < 0 once the vertex is matched
+    int32_t stamp;  // (step + 1) << 6 | lane of the last local-repair visit
 };
 
 enum : int32_t { kSkNone = 0, kSkFixed = 1, kSkAdaptive = 2, kSkLocal = 3 };
@@ -51,13 +60,14 @@ struct TrajArgs {
     const float *r0, *c0;      // shared outer scaling, nullptr = all ones
     const uint16_t *deg0;      // leaf template [n_leaf]
     const uint32_t *tree0;     // internal-node template [tree.total]
+    const int32_t *mate0_r;    // perfect matching of the filtered input, or nullptr
+    const int32_t *mate0_c;
     int32_t n_leaf;
     TreeLayout tree;
     StateLayout st;
     int32_t ok0;               // 0: the input has no perfect matching
     int32_t vertex_rule, sk_policy, dm_policy, K;
     int32_t scaled;            // proposal uses r/c
-    int32_t own_rc;            // per-trajectory r/c copies
     double theta_th, theta_tr;
     uint64_t seed;
     uint32_t b;
@@ -69,6 +79,9 @@ struct TrajArgs {
     int32_t *counters;         // [count][4] or nullptr
     uint32_t *work_next;       // work counter (zeroed before launch)
     uint32_t *err;             // internal-consistency error bits (zeroed before launch)
+    unsigned long long *work_totals;  // [5] adjacency entries scanned at the two
+                                      // endpoints, degree decrements, local-repair
+                                      // entries, local values, full SK sweeps
     char *hbm_state;           // HBM tier: base of per-wave slots; nullptr = LDS tier
     uint64_t hbm_stride;
     int32_t lds_state_bytes;   // LDS tier: bytes of state per wave
@@ -76,71 +89,71 @@ struct TrajArgs {
 };
 
 // ------------------------------------------------------------------ views
+template <bool OWN, bool DM, bool WT>
 struct Traj {
     const TrajArgs &a;
     uint16_t *deg;
     uint32_t *tree;
-    float *r, *c;
-    int32_t *stamp, *lst_a, *lst_b, *loc_r, *loc_c;
-    float *new_r, *new_c;
+    Rec *rec;
+    int32_t *lst_a, *lst_b, *loc_r, *loc_c;
+    float *new_v;
     uint32_t *rem;
+    int32_t *mate_r, *mate_c, *ws;
     int32_t n;
 
     __device__ Traj(const TrajArgs &args, char *state, uint32_t *tree_lds)
         : a(args), tree(tree_lds), n(args.A.n) {
         const StateLayout &s = args.st;
         deg = reinterpret_cast<uint16_t *>(state + s.deg);
-        r = args.own_rc ? reinterpret_cast<float *>(state + s.r) : nullptr;
-        c = args.own_rc ? reinterpret_cast<float *>(state + s.c) : nullptr;
-        stamp = reinterpret_cast<int32_t *>(state + s.stamp);
+        rec = OWN ? reinterpret_cast<Rec *>(state + s.rec) : nullptr;
         lst_a = reinterpret_cast<int32_t *>(state + s.lst_a);
         lst_b = reinterpret_cast<int32_t *>(state + s.lst_b);
         loc_r = reinterpret_cast<int32_t *>(state + s.loc_r);
         loc_c = reinterpret_cast<int32_t *>(state + s.loc_c);
-        new_r = reinterpret_cast<float *>(state + s.new_r);
-        new_c = reinterpret_cast<float *>(state + s.new_c);
-        rem = args.dm_policy != kDmNone ? reinterpret_cast<uint32_t *>(state + s.rem) : nullptr;
+        new_v = reinterpret_cast<float *>(state + s.new_v);
+        rem = DM ? reinterpret_cast<uint32_t *>(state + s.rem) : nullptr;
+        mate_r = reinterpret_cast<int32_t *>(state + s.mate_r);
+        mate_c = reinterpret_cast<int32_t *>(state + s.mate_c);
+        ws = reinterpret_cast<int32_t *>(state + s.ws);
     }
 
     __device__ __forceinline__ bool active(int32_t x) const { return deg[x] != kRetired; }
     __device__ __forceinline__ bool removed(int32_t e) const {
-        return rem != nullptr && ((rem[e >> 5] >> (e & 31)) & 1u);
+        if (!DM) return false;
+        return (rem[e >> 5] >> (e & 31)) & 1u;
     }
-    __device__ __forceinline__ float rv(int32_t i) const {
-        return r ? r[i] : (a.r0 ? a.r0[i] : 1.0f);
+    // scaling value of vertex y (r_y for a row, c_{y-n} for a column)
+    __device__ __forceinline__ float scale(int32_t y) const {
+        if (OWN) return rec[y].s;
+        if (y < n) return a.r0 ? a.r0[y] : 1.0f;
+        return a.c0 ? a.c0[y - n] : 1.0f;
     }
-    __device__ __forceinline__ float cv(int32_t j) const {
-        return c ? c[j] : (a.c0 ? a.c0[j] : 1.0f);
-    }
-    // neighbour list of vertex x: [beg, end) in CSR (row) or CSC (column)
     __device__ __forceinline__ void list(int32_t x, int32_t &beg, int32_t &end) const {
         if (x < n) { beg = a.A.row_ptr[x]; end = a.A.row_ptr[x + 1]; }
         else { beg = a.A.col_ptr[x - n]; end = a.A.col_ptr[x - n + 1]; }
     }
-    // entry p of vertex x's list: neighbour id, CSR edge id, value
+    // entry p of a list: neighbour vertex id, CSR edge id, value
     __device__ __forceinline__ void entry(bool row, int32_t p, int32_t &y, int32_t &e, float &bv) const {
         if (row) {
             y = n + a.A.col_idx[p];
             e = p;
-            bv = a.A.val ? a.A.val[p] : 1.0f;
+            bv = WT ? a.A.val[p] : 1.0f;
         } else {
             y = a.A.row_idx[p];
-            e = rem ? a.A.csc2csr[p] : 0;
-            bv = a.A.val_csc ? a.A.val_csc[p] : 1.0f;
+            e = DM ? a.A.csc2csr[p] : 0;
+            bv = WT ? a.A.val_csc[p] : 1.0f;
         }
     }
 
     // ------------------------------------------------------ min-tree
     __device__ __forceinline__ uint32_t *level(int k) const { return tree + a.tree.off[k]; }
 
-    // lower a node chain after deg[x] dropped to d
     __device__ __forceinline__ void tree_lower(int32_t x, uint32_t d) const {
         atomicMin(level(0) + (x >> 8), d);
         if (a.tree.levels > 1) atomicMin(level(1) + (x >> 14), d);
         if (a.tree.levels > 2) atomicMin(level(2) + (x >> 20), d);
     }
 
-    // min of the 256 leaves of group g, computed by the whole wave
     __device__ __forceinline__ uint32_t leaf_group_min(int32_t g) const {
         const int l = lane_id();
         const uint2 q = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
@@ -148,13 +161,8 @@ struct Traj {
         return wave_min_u32(m);
     }
 
-    // recompute the chain above vertex x (after x was retired)
-    __device__ void tree_refresh(int32_t x) const {
+    __device__ void refresh_upper(int32_t g) const {
         const int l = lane_id();
-        int32_t g = x >> 8;
-        uint32_t m = leaf_group_min(g);
-        if (l == 0) level(0)[g] = m;
-        wave_fence();
         for (int k = 1; k < a.tree.levels; ++k) {
             const int32_t h = g >> 6;
             const int32_t idx = 64 * h + l;
@@ -166,8 +174,45 @@ struct Traj {
         }
     }
 
-    // active vertex of minimum degree, smallest id; returns the degree
-    __device__ uint32_t select_min(int32_t &vsel) const {
+    // recompute the chain above vertex x from memory
+    __device__ void tree_refresh(int32_t x) const {
+        const int32_t g = x >> 8;
+        const uint32_t m = leaf_group_min(g);
+        if (lane_id() == 0) level(0)[g] = m;
+        wave_fence();
+        refresh_upper(g);
+    }
+
+    // rebuild every internal node from the leaves
+    __device__ void tree_rebuild() const {
+        const int l = lane_id();
+        for (int32_t g = 0; g < a.tree.size[0]; ++g) {
+            const uint32_t m = leaf_group_min(g);
+            if (l == 0) level(0)[g] = m;
+        }
+        wave_fence();
+        for (int k = 1; k < a.tree.levels; ++k) {
+            for (int32_t h = 0; h < a.tree.size[k]; ++h) {
+                const int32_t idx = 64 * h + l;
+                uint32_t v = idx < a.tree.size[k - 1] ? level(k - 1)[idx] : 0xFFFFFFFFu;
+                v = wave_min_u32(v);
+                if (l == 0) level(k)[h] = v;
+            }
+            wave_fence();
+        }
+    }
+
+    __device__ __forceinline__ uint32_t global_min() const {
+        const int top = a.tree.levels - 1;
+        const int l = lane_id();
+        uint32_t v = l < a.tree.size[top] ? level(top)[l] : 0xFFFFFFFFu;
+        return wave_min_u32(v);
+    }
+
+    // Minimum-degree selection; also hands back the leaf group of the
+    // selected vertex and this lane's four leaves of it, so the group
+    // minimum can be refreshed from registers after the step.
+    __device__ bool select_min(int32_t &vsel, int32_t &gsel, uint2 &leaves) const {
         const int l = lane_id();
         const int top = a.tree.levels - 1;
         uint32_t v = l < a.tree.size[top] ? level(top)[l] : 0xFFFFFFFFu;
@@ -176,27 +221,21 @@ struct Traj {
         int32_t g = __ffsll((unsigned long long)hit) - 1;
         for (int k = top - 1; k >= 0 && hit; --k) {
             const int32_t idx = 64 * g + l;
-            uint32_t w = idx < a.tree.size[k] ? level(k)[idx] : 0xFFFFFFFFu;
+            const uint32_t w = idx < a.tree.size[k] ? level(k)[idx] : 0xFFFFFFFFu;
             hit = ballot(w == m);
             g = 64 * g + __ffsll((unsigned long long)hit) - 1;
         }
-        if (!hit) { vsel = -1; return m; }  // inconsistent tree: caller aborts
-        const uint2 q = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
-        const uint32_t d0 = q.x & 0xFFFFu, d1 = q.x >> 16, d2 = q.y & 0xFFFFu, d3 = q.y >> 16;
+        if (!hit) return false;
+        leaves = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
+        const uint32_t d0 = leaves.x & 0xFFFFu, d1 = leaves.x >> 16, d2 = leaves.y & 0xFFFFu,
+                       d3 = leaves.y >> 16;
         const int j = d0 == m ? 0 : d1 == m ? 1 : d2 == m ? 2 : d3 == m ? 3 : 4;
         hit = ballot(j < 4);
-        if (!hit) { vsel = -1; return m; }
+        if (!hit) return false;
         const int src = __ffsll((unsigned long long)hit) - 1;
-        const int jj = read_lane(j, src);
-        vsel = 256 * g + 4 * src + jj;
-        return m;
-    }
-
-    __device__ __forceinline__ uint32_t global_min() const {
-        const int top = a.tree.levels - 1;
-        const int l = lane_id();
-        uint32_t v = l < a.tree.size[top] ? level(top)[l] : 0xFFFFFFFFu;
-        return wave_min_u32(v);
+        vsel = 256 * g + 4 * src + read_lane(j, src);
+        gsel = g;
+        return true;
     }
 
     // ------------------------------------------------------------ SK
@@ -210,12 +249,12 @@ struct Traj {
             for (int32_t p = a.A.col_ptr[j]; p < a.A.col_ptr[j + 1]; ++p) {
                 const int32_t i = a.A.row_idx[p];
                 if (!active(i)) continue;
-                if (rem && removed(a.A.csc2csr[p])) continue;
-                const float bv = a.A.val_csc ? a.A.val_csc[p] : 1.0f;
-                const float prod = bv * r[i];
+                if (DM && removed(a.A.csc2csr[p])) continue;
+                const float bv = WT ? a.A.val_csc[p] : 1.0f;
+                const float prod = bv * rec[i].s;
                 acc = acc + prod;
             }
-            if (acc != 0.0f) c[j] = 1.0f / acc;
+            if (acc != 0.0f) rec[n + j].s = 1.0f / acc;
         }
         wave_fence();
         for (int32_t i = l; i < n; i += kWave) {
@@ -224,139 +263,431 @@ struct Traj {
             for (int32_t e = a.A.row_ptr[i]; e < a.A.row_ptr[i + 1]; ++e) {
                 const int32_t j = a.A.col_idx[e];
                 if (!active(n + j) || removed(e)) continue;
-                const float bv = a.A.val ? a.A.val[e] : 1.0f;
-                const float prod = bv * c[j];
+                const float bv = WT ? a.A.val[e] : 1.0f;
+                const float prod = bv * rec[n + j].s;
                 acc = acc + prod;
             }
-            if (acc != 0.0f) r[i] = 1.0f / acc;
+            if (acc != 0.0f) rec[i].s = 1.0f / acc;
         }
         wave_fence();
     }
 
-    // append the active, non-removed neighbours of vertex x that are not
-    // yet stamped with `mark` to out[*cnt...]; x's own list entries are
-    // distinct, so one pass of the wave needs no intra-wave deduplication
-    __device__ void gather_unmarked(int32_t x, int32_t mark, int32_t *out, int32_t &cnt) const {
+    // Sum of B_xy * s_y over the residual neighbours y of vertex x in list
+    // order (binary32, no FMA); loads are issued eight entries at a time.
+    __device__ float residual_sum(int32_t x) const {
+        const bool row = x < n;
         int32_t beg, end;
         list(x, beg, end);
+        float acc = 0.0f;
+        for (int32_t p0 = beg; p0 < end; p0 += 8) {
+            int32_t y[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t p = p0 + i < end ? p0 + i : end - 1;
+                y[i] = row ? n + a.A.col_idx[p] : a.A.row_idx[p];
+            }
+            float sv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sv[i] = rec[y[i]].s;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t p = p0 + i;
+                if (p < end && sv[i] >= 0.0f) {
+                    if (DM) {
+                        const int32_t e = row ? p : a.A.csc2csr[p];
+                        if (removed(e)) continue;
+                    }
+                    const float bv = WT ? (row ? a.A.val[p] : a.A.val_csc[p]) : 1.0f;
+                    const float prod = bv * sv[i];
+                    acc = acc + prod;
+                }
+            }
+        }
+        return acc;
+    }
+
+    // ------------------------------------------------- inner support filter
+    // Alg. 2 InnerDM on the child residual: repair the kept perfect matching
+    // (one BFS augmentation per row that lost its partner), strongly
+    // connected components of the contracted alternating digraph (matched
+    // pair (i, mate_r[i]) = node i; entry (i, j) off the matching gives the
+    // arc mate_c[j] -> i) by an iterative Tarjan, then remove every entry
+    // off the matching whose endpoints lie in different components.
+    // Sequential parts run on lane 0; returns false if the child has no
+    // perfect matching.
+    __device__ bool augment_from(int32_t s, int32_t *queue, int32_t *parent, int32_t *vis,
+                                 int32_t stamp) const {
+        int32_t head = 0, tail = 0, found = -1;
+        queue[tail++] = s;
+        while (head < tail && found < 0) {
+            const int32_t i = queue[head++];
+            for (int32_t e = a.A.row_ptr[i]; e < a.A.row_ptr[i + 1]; ++e) {
+                const int32_t j = a.A.col_idx[e];
+                if (!active(n + j) || removed(e) || vis[j] == stamp) continue;
+                vis[j] = stamp;
+                parent[j] = i;
+                if (mate_c[j] < 0) { found = j; break; }
+                queue[tail++] = mate_c[j];
+            }
+        }
+        if (found < 0) return false;
+        int32_t j = found;
+        for (;;) {
+            const int32_t i = parent[j];
+            const int32_t nj = mate_r[i];
+            mate_r[i] = j;
+            mate_c[j] = i;
+            if (i == s) break;
+            j = nj;
+        }
+        return true;
+    }
+
+    __device__ bool dm_sequential() const {
+        int32_t *queue = ws, *parent = ws + n, *vis = ws + 2 * n;
+        for (int32_t j = 0; j < n; ++j) {
+            vis[j] = 0;
+            if (active(n + j) && mate_c[j] >= 0 && !active(mate_c[j])) mate_c[j] = -1;
+        }
+        int32_t stamp = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (!active(i)) continue;
+            const int32_t j = mate_r[i];
+            if (j >= 0 && active(n + j)) continue;
+            mate_r[i] = -1;
+            if (!augment_from(i, queue, parent, vis, ++stamp)) return false;
+        }
+        // Tarjan over active rows; comp[x] = id of x's component
+        int32_t *idx = ws, *low = ws + n, *comp = ws + 2 * n, *stk = ws + 3 * n, *fnode = ws + 4 * n,
+                *fpos = ws + 5 * n;
+        for (int32_t i = 0; i < n; ++i) { idx[i] = -1; comp[i] = -1; }
+        int32_t counter = 0, sp = 0;
+        for (int32_t root = 0; root < n; ++root) {
+            if (!active(root) || idx[root] >= 0) continue;
+            int32_t top = 0;
+            fnode[0] = root;
+            fpos[0] = a.A.col_ptr[mate_r[root]];
+            idx[root] = low[root] = counter++;
+            stk[sp++] = root;
+            while (top >= 0) {
+                const int32_t x = fnode[top];
+                const int32_t jm = mate_r[x];
+                const int32_t end = a.A.col_ptr[jm + 1];
+                bool descended = false;
+                while (fpos[top] < end) {
+                    const int32_t p = fpos[top]++;
+                    const int32_t y = a.A.row_idx[p];
+                    if (y == x || !active(y) || removed(a.A.csc2csr[p])) continue;
+                    if (idx[y] < 0) {
+                        ++top;
+                        fnode[top] = y;
+                        fpos[top] = a.A.col_ptr[mate_r[y]];
+                        idx[y] = low[y] = counter++;
+                        stk[sp++] = y;
+                        descended = true;
+                        break;
+                    }
+                    if (comp[y] < 0 && idx[y] < low[x]) low[x] = idx[y];
+                }
+                if (descended) continue;
+                if (low[x] == idx[x]) {
+                    int32_t z;
+                    do { z = stk[--sp]; comp[z] = x; } while (z != x);
+                }
+                --top;
+                if (top >= 0 && low[x] < low[fnode[top]]) low[fnode[top]] = low[x];
+            }
+        }
+        return true;
+    }
+
+    // remove entries off the matching whose endpoints lie in different
+    // components (bitmap words in parallel), recount degrees, rebuild tree
+    __device__ void dm_apply() const {
+        const int l = lane_id();
+        const int32_t *comp = ws + 2 * n;
+        const int32_t words = (a.A.m + 31) / 32;
+        for (int32_t w = l; w < words; w += kWave) {
+            uint32_t bits = rem[w];
+            for (int32_t b = 0; b < 32; ++b) {
+                const int32_t e = 32 * w + b;
+                if (e >= a.A.m || ((bits >> b) & 1u)) continue;
+                const int32_t i = a.A.edge_row[e];
+                const int32_t j = a.A.col_idx[e];
+                if (!active(i) || !active(n + j) || mate_r[i] == j) continue;
+                if (comp[i] != comp[mate_c[j]]) bits |= 1u << b;
+            }
+            rem[w] = bits;
+        }
+        wave_fence();
+        for (int32_t x = l; x < 2 * n; x += kWave) {
+            if (!active(x)) continue;
+            int32_t beg, end, c = 0;
+            list(x, beg, end);
+            const bool row = x < n;
+            for (int32_t p = beg; p < end; ++p) {
+                int32_t y, e; float bv;
+                entry(row, p, y, e, bv);
+                if (active(y) && !removed(e)) ++c;
+            }
+            deg[x] = (uint16_t)c;
+        }
+        wave_fence();
+        tree_rebuild();
+    }
+};
+
+// ------------------------------------------------------------ helpers
+__device__ __forceinline__ uint64_t lemire_from(uint64_t x, uint64_t W, uint64_t seed, uint32_t k,
+                                                uint32_t b, uint32_t t) {
+    const uint64_t lo = x * W;
+    if (lo < W) {
+        const uint64_t thr = (0ull - W) % W;
+        if (lo < thr) return uniform_below(seed, k, b, t, 1u, W);
+    }
+    return __umul64hi(x, W);
+}
+
+// last lane whose exclusive offset is <= f (offsets non-decreasing)
+__device__ __forceinline__ int owner_lane(int32_t f, int32_t off) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        const int32_t oc = __shfl(off, cand < kWave ? cand : kWave - 1);
+        if (cand < kWave && oc <= f) lo = cand;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total) {
+    const int l = lane_id();
+    int32_t v = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(v, o);
+        if (l >= o) v += y;
+    }
+    total = __shfl(v, kWave - 1);
+    return v - x;
+}
+
+// Eq. (local).  rho_y: a column vertex of N_t(rho)\{gam} held by this lane
+// (or -1); gam_y: a row of N_t(gam)\{rho} (or -1).  R_loc / C_loc membership
+// is marked with stamps (step+1) << 6 | lane; when several lanes reach the
+// same vertex in one instruction the lane whose stamp survives keeps it.
+template <class TT>
+__device__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
+                                   uint64_t *work) {
+    const TrajArgs &a = T.a;
+    const int l = lane_id();
+    const int32_t n = T.n;
+    const int32_t mark = t + 1;
+    const int32_t mine = (mark << 6) | l;
+    int32_t nc = 0, nr = 0;
+    {
+        const uint64_t mc = ballot(rho_y >= 0);
+        if (rho_y >= 0) { T.rec[rho_y].stamp = mine; T.loc_c[rank_below(mc)] = rho_y - n; }
+        nc = __popcll(mc);
+        const uint64_t mr = ballot(gam_y >= 0);
+        if (gam_y >= 0) { T.rec[gam_y].stamp = mine; T.loc_r[rank_below(mr)] = gam_y; }
+        nr = __popcll(mr);
+    }
+    int32_t gb = 0, gl = 0, rb = 0, rl = 0;
+    if (gam_y >= 0) { gb = a.A.row_ptr[gam_y]; gl = a.A.row_ptr[gam_y + 1] - gb; }
+    if (rho_y >= 0) { rb = a.A.col_ptr[rho_y - n]; rl = a.A.col_ptr[rho_y - n + 1] - rb; }
+    int32_t TG, TR;
+    const int32_t og = wave_excl_scan_i32(gl, TG);
+    const int32_t orr = wave_excl_scan_i32(rl, TR);
+    wave_fence();
+    for (int32_t base = 0; base < TG + TR; base += kWave) {
+        const int32_t f = base + l;
+        const bool in_g = f < TG;
+        const bool in_r = !in_g && f < TG + TR;
+        // every lane takes part in every shuffle (no divergent cross-lane reads)
+        const int32_t fg = in_g ? f : 0;
+        const int og_o = owner_lane(fg, og);
+        const int32_t gb_o = __shfl(gb, og_o), og_v = __shfl(og, og_o);
+        const int32_t fr = in_r ? f - TG : 0;
+        const int or_o = owner_lane(fr, orr);
+        const int32_t rb_o = __shfl(rb, or_o), or_v = __shfl(orr, or_o);
+        int32_t tgt = -1, e = 0;
+        if (in_g) {
+            const int32_t p = gb_o + (fg - og_v);
+            tgt = n + a.A.col_idx[p];
+            e = p;
+        } else if (in_r) {
+            const int32_t p = rb_o + (fr - or_v);
+            tgt = a.A.row_idx[p];
+            e = T.rem ? a.A.csc2csr[p] : 0;
+        }
+        bool cand = false;
+        if (tgt >= 0) {
+            const Rec rc = T.rec[tgt];
+            cand = rc.s >= 0.0f && (rc.stamp >> 6) != mark && !T.removed(e);
+        }
+        if (cand) T.rec[tgt].stamp = mine;
+        wave_fence();
+        const bool win = cand && T.rec[tgt].stamp == mine;
+        const uint64_t wc = ballot(win && in_g);
+        const uint64_t wr = ballot(win && in_r);
+        if (win && in_g) T.loc_c[nc + rank_below(wc)] = tgt - n;
+        if (win && in_r) T.loc_r[nr + rank_below(wr)] = tgt;
+        nc += __popcll(wc);
+        nr += __popcll(wr);
+    }
+    wave_fence();
+    const int32_t ne = nr + nc;
+    uint64_t summed = 0;
+    if (ne <= kWave) {
+        int32_t x = -1;
+        float val = 0.0f;
+        if (l < ne) x = l < nr ? T.loc_r[l] : n + T.loc_c[l - nr];
+        if (x >= 0) {
+            const float old = T.rec[x].s;
+            const float acc = T.residual_sum(x);
+            val = acc != 0.0f ? 1.0f / acc : old;
+            int32_t b0, e0;
+            T.list(x, b0, e0);
+            summed = e0 - b0;
+        }
+        wave_fence();
+        if (x >= 0) T.rec[x].s = val;
+    } else {
+        for (int32_t idx = l; idx < ne; idx += kWave) {
+            const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
+            const float old = T.rec[x].s;
+            const float acc = T.residual_sum(x);
+            int32_t b0, e0;
+            T.list(x, b0, e0);
+            summed += e0 - b0;
+            T.new_v[idx] = acc != 0.0f ? 1.0f / acc : old;
+        }
+        wave_fence();
+        for (int32_t idx = l; idx < ne; idx += kWave) {
+            const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
+            T.rec[x].s = T.new_v[idx];
+        }
+    }
+    wave_fence();
+    work[2] += (uint64_t)(TG + TR) + wave_sum_u64(summed);
+    work[3] += (uint64_t)ne;
+}
+
+// Eq. (local) with lists kept in memory (either list longer than a wave):
+// the same sets and values, built one list at a time.
+template <class TT>
+__device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t k_rho, int32_t skip_rho,
+                                   const int32_t *gam_list, int32_t k_gam, int32_t skip_gam, int32_t t,
+                                   uint64_t *work) {
+    const int l = lane_id();
+    const int32_t n = T.n;
+    const int32_t mark = t + 1;
+    int32_t nc = 0, nr = 0;
+    uint64_t gathered = 0;
+    for (int32_t base = 0; base < k_rho; base += kWave) {
+        const int32_t idx = base + l;
+        const int32_t y = idx < k_rho ? rho_list[idx] : -1;
+        const bool take = idx < k_rho && y != skip_rho;
+        const uint64_t msk = ballot(take);
+        if (take) { T.rec[y].stamp = mark << 6; T.loc_c[nc + rank_below(msk)] = y - n; }
+        nc += __popcll(msk);
+    }
+    for (int32_t base = 0; base < k_gam; base += kWave) {
+        const int32_t idx = base + l;
+        const int32_t y = idx < k_gam ? gam_list[idx] : -1;
+        const bool take = idx < k_gam && y != skip_gam;
+        const uint64_t msk = ballot(take);
+        if (take) { T.rec[y].stamp = mark << 6; T.loc_r[nr + rank_below(msk)] = y; }
+        nr += __popcll(msk);
+    }
+    wave_fence();
+    // child neighbours, one source vertex at a time (its entries are distinct)
+    auto gather = [&](int32_t x, int32_t *out, int32_t &cnt, bool to_col) {
+        int32_t beg, end;
+        T.list(x, beg, end);
         const bool row = x < n;
+        gathered += end - beg;
         for (int32_t base = beg; base < end; base += kWave) {
-            const int32_t p = base + lane_id();
+            const int32_t p = base + l;
             bool take = false;
             int32_t y = 0;
             if (p < end) {
                 int32_t e; float bv;
-                entry(row, p, y, e, bv);
-                take = active(y) && !removed(e) && stamp[y] != mark;
+                T.entry(row, p, y, e, bv);
+                const Rec rc = T.rec[y];
+                take = rc.s >= 0.0f && !T.removed(e) && (rc.stamp >> 6) != mark;
             }
             const uint64_t msk = ballot(take);
             if (take) {
-                stamp[y] = mark;
-                out[cnt + rank_below(msk)] = y;
+                T.rec[y].stamp = mark << 6;
+                out[cnt + rank_below(msk)] = to_col ? y - n : y;
             }
             cnt += __popcll(msk);
             wave_fence();
         }
+    };
+    for (int32_t q = 0; q < k_gam; ++q) {
+        const int32_t i = gam_list[q];
+        if (i != skip_gam) gather(i, T.loc_c, nc, true);
     }
-
-    __device__ float repair_row(int32_t i) const {
-        float acc = 0.0f;
-        for (int32_t e = a.A.row_ptr[i]; e < a.A.row_ptr[i + 1]; ++e) {
-            const int32_t j = a.A.col_idx[e];
-            if (!active(n + j) || removed(e)) continue;
-            const float bv = a.A.val ? a.A.val[e] : 1.0f;
-            const float prod = bv * c[j];
-            acc = acc + prod;
-        }
-        return acc != 0.0f ? 1.0f / acc : r[i];
+    for (int32_t q = 0; q < k_rho; ++q) {
+        const int32_t y = rho_list[q];
+        if (y != skip_rho) gather(y, T.loc_r, nr, false);
     }
-
-    __device__ float repair_col(int32_t j) const {
-        float acc = 0.0f;
-        for (int32_t p = a.A.col_ptr[j]; p < a.A.col_ptr[j + 1]; ++p) {
-            const int32_t i = a.A.row_idx[p];
-            if (!active(i)) continue;
-            if (rem && removed(a.A.csc2csr[p])) continue;
-            const float bv = a.A.val_csc ? a.A.val_csc[p] : 1.0f;
-            const float prod = bv * r[i];
-            acc = acc + prod;
-        }
-        return acc != 0.0f ? 1.0f / acc : c[j];
+    wave_fence();
+    const int32_t ne = nr + nc;
+    uint64_t summed = 0;
+    for (int32_t idx = l; idx < ne; idx += kWave) {
+        const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
+        const float old = T.rec[x].s;
+        const float acc = T.residual_sum(x);
+        int32_t b0, e0;
+        T.list(x, b0, e0);
+        summed += e0 - b0;
+        T.new_v[idx] = acc != 0.0f ? 1.0f / acc : old;
     }
-
-    // Eq. (local): rho_list = N_t(rho)\{gam} (column ids n+j), gam_list =
-    // N_t(gam)\{rho} (row ids); `skip` is excluded from the list it lies in
-    __device__ void local_repair(const int32_t *rho_list, int32_t k_rho, int32_t skip_rho,
-                                 const int32_t *gam_list, int32_t k_gam, int32_t skip_gam,
-                                 int32_t mark) const {
-        const int l = lane_id();
-        int32_t nc = 0, nr = 0;
-        // C_loc: rho's other columns, then the child columns of gam's other rows
-        for (int32_t base = 0; base < k_rho; base += kWave) {
-            const int32_t idx = base + l;
-            const int32_t y = idx < k_rho ? rho_list[idx] : -1;
-            const bool take = idx < k_rho && y != skip_rho;
-            const uint64_t msk = ballot(take);
-            if (take) { stamp[y] = mark; loc_c[nc + rank_below(msk)] = y - n; }
-            nc += __popcll(msk);
-        }
-        // R_loc: gam's other rows first
-        for (int32_t base = 0; base < k_gam; base += kWave) {
-            const int32_t idx = base + l;
-            const int32_t y = idx < k_gam ? gam_list[idx] : -1;
-            const bool take = idx < k_gam && y != skip_gam;
-            const uint64_t msk = ballot(take);
-            if (take) { stamp[y] = mark; loc_r[nr + rank_below(msk)] = y; }
-            nr += __popcll(msk);
-        }
-        wave_fence();
-        for (int32_t q = 0; q < k_gam; ++q) {
-            const int32_t i = gam_list[q];
-            if (i == skip_gam) continue;
-            const int32_t before = nc;
-            gather_unmarked(i, mark, loc_c, nc);
-            // stored as column vertex ids; convert the new ones to column indices
-            for (int32_t idx = before + l; idx < nc; idx += kWave) loc_c[idx] -= n;
-            wave_fence();
-        }
-        for (int32_t q = 0; q < k_rho; ++q) {
-            const int32_t y = rho_list[q];
-            if (y == skip_rho) continue;
-            gather_unmarked(y, mark, loc_r, nr);
-        }
-        wave_fence();
-        for (int32_t idx = l; idx < nr; idx += kWave) new_r[idx] = repair_row(loc_r[idx]);
-        for (int32_t idx = l; idx < nc; idx += kWave) new_c[idx] = repair_col(loc_c[idx]);
-        wave_fence();
-        for (int32_t idx = l; idx < nr; idx += kWave) r[loc_r[idx]] = new_r[idx];
-        for (int32_t idx = l; idx < nc; idx += kWave) c[loc_c[idx]] = new_c[idx];
-        wave_fence();
+    wave_fence();
+    for (int32_t idx = l; idx < ne; idx += kWave) {
+        const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
+        T.rec[x].s = T.new_v[idx];
     }
-};
+    wave_fence();
+    work[2] += gathered + wave_sum_u64(summed);
+    work[3] += (uint64_t)ne;
+}
 
 // ------------------------------------------------------------------ kernel
-__device__ void run_trajectory(const TrajArgs &a, Traj &T, int64_t q) {
+template <int SK, bool DM, bool WT>
+__device__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, WT> &T, int64_t q,
+                               uint64_t *work) {
+    constexpr bool OWN = SK != kSkNone;
     const int l = lane_id();
     const int32_t n = a.A.n;
     const uint32_t k = (uint32_t)(a.first + q);
     int32_t *path = a.path ? a.path + (size_t)q * 2 * n : nullptr;
 
-    // ---- initial state: template degrees, tree, scaling copies, marks
+    // ---- initial state: template degrees, tree, scaling values, matching
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.deg0);
         uint4 *dst = reinterpret_cast<uint4 *>(T.deg);
         for (int32_t i = l; i < a.n_leaf / 8; i += kWave) dst[i] = src[i];
         for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = a.tree0[i];
-        if (a.own_rc) {
-            for (int32_t i = l; i < n; i += kWave) {
-                T.r[i] = a.r0 ? a.r0[i] : 1.0f;
-                T.c[i] = a.c0 ? a.c0[i] : 1.0f;
+        if (OWN) {
+            for (int32_t x = l; x < 2 * n; x += kWave) {
+                float s = 1.0f;
+                if (x < n) { if (a.r0) s = a.r0[x]; }
+                else if (a.c0) s = a.c0[x - n];
+                T.rec[x] = Rec{s, 0};
             }
         }
-        if (a.sk_policy == kSkLocal)
-            for (int32_t i = l; i < 2 * n; i += kWave) T.stamp[i] = 0;
-        if (T.rem)
+        if (DM) {
             for (int32_t i = l; i < (a.A.m + 31) / 32; i += kWave) T.rem[i] = 0;
+            for (int32_t i = l; i < n; i += kWave) {
+                T.mate_r[i] = a.mate0_r ? a.mate0_r[i] : -1;
+                T.mate_c[i] = a.mate0_c ? a.mate0_c[i] : -1;
+            }
+        }
         if (path)
             for (int32_t i = l; i < 2 * n; i += kWave) path[i] = -1;
         wave_fence();
@@ -370,105 +701,135 @@ __device__ void run_trajectory(const TrajArgs &a, Traj &T, int64_t q) {
     bool alive = a.ok0 != 0;
 
     for (int32_t t = 0; alive && t < n; ++t) {
+        const uint64_t R0 = rand64(a.seed, k, a.b, (uint32_t)t, 0u);
         // ---- choose the vertex
-        int32_t v;
+        int32_t v = -1, gsel = -1;
+        uint2 gleaves = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
         if (a.vertex_rule == 1) v = t;
-        else T.select_min(v);
+        else if (!T.select_min(v, gsel, gleaves)) v = -1;
         if (v < 0 || v >= 2 * n) {  // internal inconsistency: report, never index
             if (l == 0) atomicOr(a.err, 1u);
             alive = false;
             break;
         }
         const bool v_row = v < n;
+        int32_t vb, ve;
+        T.list(v, vb, ve);
+        const bool fast_v = ve - vb <= kWave;
 
-        // ---- pass A: candidates N_t(v) (into lst_a), their count, max score
-        int32_t beg, end;
-        T.list(v, beg, end);
-        int32_t kc = 0;
-        float lmax = 0.0f;
-        for (int32_t base = beg; base < end; base += kWave) {
-            const int32_t p = base + l;
-            bool cand = false;
-            int32_t y = 0, e = 0;
-            float bv = 0.0f;
-            if (p < end) {
-                T.entry(v_row, p, y, e, bv);
-                cand = T.active(y) && !T.removed(e);
+        // ---- candidates N_t(v), proposal of Eq. (q), draw, pick
+        int32_t kc = 0, u = -1;
+        float b_vu = 1.0f;
+        uint64_t W = 0, w_u = 1;
+        uint32_t d_u = 0;
+        int32_t cy = -1;   // this lane's candidate (lists up to a wave)
+        uint32_t cd = 0;
+        bool cand = false;
+        if (fast_v) {
+            const int32_t p = vb + l;
+            int32_t e = 0;
+            float bv = 0.0f, sc = 1.0f;
+            if (p < ve) {
+                T.entry(v_row, p, cy, e, bv);
+                cd = T.deg[cy];
+                if (a.scaled) sc = T.scale(cy);
+                cand = cd != kRetired && !T.removed(e);
             }
-            const uint64_t msk = ballot(cand);
+            kc = __popcll(ballot(cand));
+            if (kc == 0) { alive = false; break; }
+            const float s = a.scaled ? bv * sc : bv;
+            const float lmax = (cand && s > 0.0f) ? s : 0.0f;
+            const float smax = wave_max_f32(lmax);
+            const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
+            uint64_t w = 0;
             if (cand) {
-                T.lst_a[kc + rank_below(msk)] = y;
-                if (a.scaled) {
-                    const float sc = v_row ? T.cv(y - n) : T.rv(y);
-                    const float s = bv * sc;
-                    lmax = (s > lmax) ? s : lmax;
-                } else {
-                    lmax = (bv > lmax) ? bv : lmax;
+                if (kc == 1 || uniform) w = 1;
+                else {
+                    const float rr = rintf((s / smax) * 16777216.0f);
+                    w = rr >= 1.0f ? (uint64_t)rr : 1ull;
                 }
             }
-            kc += __popcll(msk);
-        }
-        if (kc == 0) { alive = false; break; }
-        const float smax = wave_max_f32(lmax);
-        const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
-
-        // ---- pass B: integer weights w_i and W
-        auto weight = [&](float s) -> uint64_t {
-            if (uniform) return 1ull;
-            const float ratio = s / smax;
-            const float rr = rintf(ratio * 16777216.0f);
-            return rr >= 1.0f ? (uint64_t)rr : 1ull;
-        };
-        auto score = [&](int32_t y, float bv) -> float {
-            if (!a.scaled) return bv;
-            const float sc = v_row ? T.cv(y - n) : T.rv(y);
-            return bv * sc;
-        };
-        uint64_t W = 0;
-        if (kc > 1) {
-            for (int32_t base = beg; base < end; base += kWave) {
+            const uint64_t incl = wave_incl_scan_u64(w);
+            W = read_lane(incl, kWave - 1);
+            const uint64_t j = kc > 1 ? lemire_from(R0, W, a.seed, k, a.b, (uint32_t)t) : 0ull;
+            const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
+            if (hm) {
+                const int src = __ffsll((unsigned long long)hm) - 1;
+                u = read_lane(cy, src);
+                b_vu = read_lane(bv, src);
+                w_u = read_lane(w, src);
+                d_u = read_lane(cd, src);
+            }
+            if (kc == 1) W = w_u;
+        } else {
+            // long list: three passes over memory, candidates into lst_a
+            float lmax = 0.0f;
+            for (int32_t base = vb; base < ve; base += kWave) {
+                const int32_t p = base + l;
+                bool c0 = false;
+                int32_t y = 0, e = 0;
+                float bv = 0.0f;
+                if (p < ve) {
+                    T.entry(v_row, p, y, e, bv);
+                    c0 = T.active(y) && !T.removed(e);
+                }
+                const uint64_t msk = ballot(c0);
+                if (c0) {
+                    T.lst_a[kc + rank_below(msk)] = y;
+                    const float s = a.scaled ? bv * T.scale(y) : bv;
+                    lmax = (s > lmax) ? s : lmax;
+                }
+                kc += __popcll(msk);
+            }
+            if (kc == 0) { alive = false; break; }
+            const float smax = wave_max_f32(lmax);
+            const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
+            auto weight_of = [&](int32_t y, float bv) -> uint64_t {
+                if (kc == 1 || uniform) return 1ull;
+                const float s = a.scaled ? bv * T.scale(y) : bv;
+                const float rr = rintf((s / smax) * 16777216.0f);
+                return rr >= 1.0f ? (uint64_t)rr : 1ull;
+            };
+            for (int32_t base = vb; base < ve; base += kWave) {
                 const int32_t p = base + l;
                 uint64_t w = 0;
-                if (p < end) {
+                if (p < ve) {
                     int32_t y, e; float bv;
                     T.entry(v_row, p, y, e, bv);
-                    if (T.active(y) && !T.removed(e)) w = weight(score(y, bv));
+                    if (T.active(y) && !T.removed(e)) w = weight_of(y, bv);
                 }
                 W += wave_sum_u64(w);
             }
-        }
-        // ---- draw u ~ q_t(.|v) and locate it (pass C)
-        const uint64_t j = kc > 1 ? uniform_below(a.seed, k, a.b, (uint32_t)t, 0u, W) : 0ull;
-        int32_t u = -1;
-        float b_vu = 1.0f;
-        uint64_t w_u = 1, pre = 0;
-        for (int32_t base = beg; base < end; base += kWave) {
-            const int32_t p = base + l;
-            uint64_t w = 0;
-            int32_t y = 0, e = 0;
-            float bv = 0.0f;
-            if (p < end) {
-                T.entry(v_row, p, y, e, bv);
-                if (T.active(y) && !T.removed(e)) w = kc > 1 ? weight(score(y, bv)) : 1ull;
+            const uint64_t j = kc > 1 ? lemire_from(R0, W, a.seed, k, a.b, (uint32_t)t) : 0ull;
+            uint64_t pre = 0;
+            for (int32_t base = vb; base < ve; base += kWave) {
+                const int32_t p = base + l;
+                uint64_t w = 0;
+                int32_t y = 0, e = 0;
+                float bv = 0.0f;
+                if (p < ve) {
+                    T.entry(v_row, p, y, e, bv);
+                    if (T.active(y) && !T.removed(e)) w = weight_of(y, bv);
+                }
+                const uint64_t incl = wave_incl_scan_u64(w) + pre;
+                const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
+                if (hm) {
+                    const int src = __ffsll((unsigned long long)hm) - 1;
+                    u = read_lane(y, src);
+                    b_vu = read_lane(bv, src);
+                    w_u = read_lane(w, src);
+                    break;
+                }
+                pre = read_lane(incl, kWave - 1);
             }
-            const uint64_t incl = wave_incl_scan_u64(w) + pre;
-            const bool hit = w != 0 && incl > j && incl - w <= j;
-            const uint64_t msk = ballot(hit);
-            if (msk) {
-                const int src = __ffsll((unsigned long long)msk) - 1;
-                u = read_lane(y, src);
-                b_vu = read_lane(bv, src);
-                w_u = read_lane(w, src);
-                break;
-            }
-            pre = read_lane(incl, kWave - 1);
+            if (kc == 1) W = w_u;
+            if (u >= 0) d_u = T.deg[u];
         }
         if (u < 0) {  // no candidate matched the draw: internal inconsistency
             if (l == 0) atomicOr(a.err, 2u);
             alive = false;
             break;
         }
-        if (kc == 1) W = w_u;
 
         // ---- importance correction X <- X * B_vu / q(u|v), extended exponent
         {
@@ -478,68 +839,137 @@ __device__ void run_trajectory(const TrajArgs &a, Traj &T, int64_t q) {
             ex += e2;
         }
         const int32_t rho = v_row ? v : u;
-        const int32_t gam = v_row ? u : v;   // column vertex id
-        const double z = (double)T.rv(rho) * (double)T.cv(gam - n);
+        const int32_t gam = v_row ? u : v;  // column vertex id
+        const double z = (double)T.scale(rho) * (double)T.scale(gam);
         if (path && l == 0) { path[2 * t] = v; path[2 * t + 1] = u; }
         h = splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);
 
-        // ---- N_t(u) \ {v} into lst_b
+        // ---- N_t(u) \ {v}
+        int32_t ub, ue;
+        T.list(u, ub, ue);
+        const bool fast_u = ue - ub <= kWave;
+        const bool u_row = u < n;
+        int32_t by = -1;
+        uint32_t bd = 0;
+        bool take = false;
         int32_t kb = 0;
-        {
-            int32_t ub, ue;
-            T.list(u, ub, ue);
-            const bool u_row = u < n;
+        if (fast_u) {
+            const int32_t p = ub + l;
+            if (p < ue) {
+                int32_t e; float bv;
+                T.entry(u_row, p, by, e, bv);
+                bd = T.deg[by];
+                take = by != v && bd != kRetired && !T.removed(e);
+            }
+            kb = __popcll(ballot(take));
+        } else {
             for (int32_t base = ub; base < ue; base += kWave) {
                 const int32_t p = base + l;
-                bool take = false;
+                bool tk = false;
                 int32_t y = 0;
                 if (p < ue) {
                     int32_t e; float bv;
                     T.entry(u_row, p, y, e, bv);
-                    take = y != v && T.active(y) && !T.removed(e);
+                    tk = y != v && T.active(y) && !T.removed(e);
                 }
-                const uint64_t msk = ballot(take);
-                if (take) T.lst_b[kb + rank_below(msk)] = y;
+                const uint64_t msk = ballot(tk);
+                if (tk) T.lst_b[kb + rank_below(msk)] = y;
                 kb += __popcll(msk);
             }
         }
+        const int32_t gu = u >> 8;
+        const uint32_t l1u_before = T.level(0)[gu];
         wave_fence();
 
         // ---- B^(t+1) = B^(t) \ {v,u}: retire both, lower their neighbours
-        if (l == 0) { T.deg[v] = kRetired; T.deg[u] = kRetired; }
-        for (int32_t idx = l; idx < kc; idx += kWave) {
-            const int32_t y = T.lst_a[idx];
-            if (y == u) continue;
-            const uint32_t d = (uint32_t)T.deg[y] - 1u;
-            T.deg[y] = (uint16_t)d;
-            T.tree_lower(y, d);
+        if (l == 0) {
+            T.deg[v] = kRetired;
+            T.deg[u] = kRetired;
+            if (OWN) { T.rec[v].s = -1.0f; T.rec[u].s = -1.0f; }
         }
-        for (int32_t idx = l; idx < kb; idx += kWave) {
-            const int32_t y = T.lst_b[idx];
-            const uint32_t d = (uint32_t)T.deg[y] - 1u;
-            T.deg[y] = (uint16_t)d;
-            T.tree_lower(y, d);
+        uint32_t dec_min_g = 0xFFFFFFFFu;  // lowest new degree inside v's leaf group
+        if (fast_v) {
+            if (cand && cy != u) {
+                const uint32_t nd = cd - 1u;
+                T.deg[cy] = (uint16_t)nd;
+                T.tree_lower(cy, nd);
+                if ((cy >> 8) == gsel) dec_min_g = nd;
+            }
+        } else {
+            for (int32_t idx = l; idx < kc; idx += kWave) {
+                const int32_t y = T.lst_a[idx];
+                if (y == u) continue;
+                const uint32_t nd = (uint32_t)T.deg[y] - 1u;
+                T.deg[y] = (uint16_t)nd;
+                T.tree_lower(y, nd);
+                if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+            }
         }
+        if (fast_u) {
+            if (take) {
+                const uint32_t nd = bd - 1u;
+                T.deg[by] = (uint16_t)nd;
+                T.tree_lower(by, nd);
+                if ((by >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+            }
+        } else {
+            for (int32_t idx = l; idx < kb; idx += kWave) {
+                const int32_t y = T.lst_b[idx];
+                const uint32_t nd = (uint32_t)T.deg[y] - 1u;
+                T.deg[y] = (uint16_t)nd;
+                T.tree_lower(y, nd);
+                if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+            }
+        }
+        work[0] += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
+        work[1] += (uint64_t)(kc - 1 + kb);
         wave_fence();
-        T.tree_refresh(v);
-        T.tree_refresh(u);
+        // refresh the group of v from the leaves read at selection time
+        if (gsel >= 0) {
+            const int32_t base_id = 256 * gsel + 4 * l;
+            uint32_t d0 = gleaves.x & 0xFFFFu, d1 = gleaves.x >> 16, d2 = gleaves.y & 0xFFFFu,
+                     d3 = gleaves.y >> 16;
+            if (base_id == v || base_id == u) d0 = 0xFFFFu;
+            if (base_id + 1 == v || base_id + 1 == u) d1 = 0xFFFFu;
+            if (base_id + 2 == v || base_id + 2 == u) d2 = 0xFFFFu;
+            if (base_id + 3 == v || base_id + 3 == u) d3 = 0xFFFFu;
+            uint32_t mm = min(min(d0, d1), min(d2, d3));
+            mm = wave_min_u32(min(mm, dec_min_g));
+            if (l == 0) T.level(0)[gsel] = mm;
+            wave_fence();
+            T.refresh_upper(gsel);
+        } else {
+            T.tree_refresh(v);
+        }
+        if (gu != gsel && d_u <= l1u_before) T.tree_refresh(u);
         steps = t + 1;
         track = track * z;
         if (t + 1 >= n) break;
 
-        if (T.global_min() == 0) { alive = false; break; }   // child dead end
+        if (T.global_min() == 0) { alive = false; break; }  // child dead end
 
-        // ---- P_DM (inner support filtering is rejected by the host for now)
-        bool run_dm = false;
-        if (a.dm_policy == kDmAll) run_dm = true;
-        else if (a.dm_policy == kDmThrs && z < a.theta_th) run_dm = true;
-        else if (a.dm_policy == kDmTrck && track < a.theta_tr) run_dm = true;
-        if (run_dm) { n_dm += 1; track = 1.0; }
+        // ---- P_DM: support filtering of the child
+        if (DM) {
+            bool run_dm = false;
+            if (a.dm_policy == kDmAll) run_dm = true;
+            else if (a.dm_policy == kDmThrs && z < a.theta_th) run_dm = true;
+            else if (a.dm_policy == kDmTrck && track < a.theta_tr) run_dm = true;
+            if (run_dm) {
+                n_dm += 1;
+                int ok = 0;
+                if (l == 0) ok = T.dm_sequential() ? 1 : 0;
+                ok = read_lane(ok, 0);
+                wave_fence();
+                if (!ok) { alive = false; break; }
+                T.dm_apply();
+                track = 1.0;
+            }
+        }
 
         // ---- P_SK on the child
-        if (a.sk_policy == kSkFixed || a.sk_policy == kSkAdaptive) {
+        if (SK == kSkFixed || SK == kSkAdaptive) {
             int nit = a.K;
-            if (a.sk_policy == kSkAdaptive) {
+            if (SK == kSkAdaptive) {
                 double want = ceil((1.0 - z) * (double)a.K);
                 if (!(want > 0.0)) want = 0.0;
                 if (want > (double)a.K) want = (double)a.K;
@@ -547,10 +977,27 @@ __device__ void run_trajectory(const TrajArgs &a, Traj &T, int64_t q) {
             }
             for (int it = 0; it < nit; ++it) T.sk_sweep();
             n_sweeps += nit;
-        } else if (a.sk_policy == kSkLocal) {
-            // rho_list = N_t(rho)\{gam}, gam_list = N_t(gam)\{rho}
-            if (v_row) T.local_repair(T.lst_a, kc, u, T.lst_b, kb, -1, t + 1);
-            else T.local_repair(T.lst_b, kb, -1, T.lst_a, kc, u, t + 1);
+            work[4] += (uint64_t)nit;
+        } else if (SK == kSkLocal) {
+            // rho_list = N_t(rho)\{gam} (columns), gam_list = N_t(gam)\{rho} (rows)
+            if (fast_v && fast_u) {
+                const int32_t other_v = (cand && cy != u) ? cy : -1;
+                const int32_t other_u = take ? by : -1;
+                if (v_row) local_repair_lanes(T, other_v, other_u, t, work);
+                else local_repair_lanes(T, other_u, other_v, t, work);
+            } else {
+                if (fast_v) {
+                    const uint64_t msk = ballot(cand);
+                    if (cand) T.lst_a[rank_below(msk)] = cy;
+                }
+                if (fast_u) {
+                    const uint64_t msk = ballot(take);
+                    if (take) T.lst_b[rank_below(msk)] = by;
+                }
+                wave_fence();
+                if (v_row) local_repair_lists(T, T.lst_a, kc, u, T.lst_b, kb, -1, t, work);
+                else local_repair_lists(T, T.lst_b, kb, -1, T.lst_a, kc, u, t, work);
+            }
             n_local += 1;
         }
     }
@@ -568,7 +1015,9 @@ __device__ void run_trajectory(const TrajArgs &a, Traj &T, int64_t q) {
     wave_fence();
 }
 
-__global__ void __launch_bounds__(256) traj_kernel(TrajArgs a) {
+template <int SK, bool DM, bool WT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SK == kSkNone ? 4 : 1, 8)))
+traj_kernel(TrajArgs a) {
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x / kWave;
     const size_t per_wave = (size_t)a.tree.total * 4 + (size_t)a.lds_state_bytes;
@@ -581,13 +1030,21 @@ __global__ void __launch_bounds__(256) traj_kernel(TrajArgs a) {
     } else {
         state = mine + (size_t)a.tree.total * 4;
     }
-    Traj T(a, state, tree);
+    const Traj<SK != kSkNone, DM, WT> T(a, state, tree);
+    uint64_t work[5] = {0, 0, 0, 0, 0};
     for (;;) {
         uint32_t q = 0;
         if (lane_id() == 0) q = atomicAdd(a.work_next, 1u);
         q = read_lane(q, 0);
         if ((int64_t)q >= a.count) break;
-        run_trajectory(a, T, (int64_t)q);
+        run_trajectory<SK, DM, WT>(a, T, (int64_t)q, work);
+    }
+    if (lane_id() == 0 && a.work_totals) {
+        atomicAdd(a.work_totals + 0, (unsigned long long)work[0]);
+        atomicAdd(a.work_totals + 1, (unsigned long long)work[1]);
+        atomicAdd(a.work_totals + 2, (unsigned long long)work[2]);
+        atomicAdd(a.work_totals + 3, (unsigned long long)work[3]);
+        atomicAdd(a.work_totals + 4, (unsigned long long)work[4]);
     }
 }
 

@@ -180,3 +180,50 @@ def test_gpu_mean_within_ci_of_ryser(gseed):
         r = est.run(0, 200000, 1000 + gseed, P.preset(name), want_logw=False, want_alive=False)["result"]
         est.close()
         assert abs(math.exp(r["log_estimate"]) / per - 1) <= 4.5 * r["rse"], (name, r)
+
+
+PAPER_PRESETS = ["fixed_all", "adaptive_threshold", "local_threshold", "adaptive_tracked", "local_tracked"]
+DM_MATS = [("small1", lambda: G.config_small(1)), ("small3", lambda: G.config_small(3)),
+           ("weighted", lambda: G.with_weights(G.planted_bernoulli(40, 0.12, 5, planted="random"), 1)),
+           ("batch60", lambda: G.planted_bernoulli(60, 5.0 / 59, 21, planted="random"))]
+
+
+@pytest.mark.parametrize("name", PAPER_PRESETS)
+@pytest.mark.parametrize("mat", DM_MATS, ids=[m[0] for m in DM_MATS])
+def test_paper_presets_with_inner_dm_bit_exact(name, mat):
+    """The five variants of Sec. 4, inner DM included, on small inputs."""
+    M = mat[1]()
+    g, o = _both(name)
+    out, orc = _compare(M, g, o, seed=13, first=0, count=200)
+    if name == "fixed_all":
+        assert out["alive"].all()  # DM at every child keeps p_match = 1
+    assert out["result"]["n_dm"] == int(orc["counters"][:, 1].sum())
+
+
+@pytest.mark.parametrize("name", ["adaptive_threshold", "local_threshold"])
+def test_batch_sized_matrix_with_inner_dm(name):
+    M = G.planted_bernoulli(300, 6.0 / 299, 77, planted="random")
+    g, o = _both(name)
+    _compare(M, g, o, seed=2, first=5, count=24)
+
+
+@pytest.mark.parametrize("name", ["local_threshold", "adaptive_tracked"])
+def test_tiers_agree_with_inner_dm(name):
+    M = G.planted_bernoulli(120, 5.0 / 119, 3, planted="random")
+    g, o = _both(name)
+    a, _ = _compare(M, g, o, seed=4, first=0, count=64, force_hbm=False)
+    b, _ = _compare(M, g, o, seed=4, first=0, count=64, force_hbm=True)
+    for k in ("logw", "alive", "path", "path_hash", "counters"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("gseed", [1, 2])
+def test_gpu_paper_presets_unbiased(gseed):
+    import paper_2608_15390_amd as P
+    M = G.config_small(gseed)
+    per = O.ryser(G.to_dense(M))
+    for name in PAPER_PRESETS:
+        est = P.PermEst(M)
+        r = est.run(0, 40000, 500 + gseed, P.preset(name), want_logw=False, want_alive=False)["result"]
+        est.close()
+        assert abs(math.exp(r["log_estimate"]) / per - 1) <= 4.5 * r["rse"], (name, r)

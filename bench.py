@@ -40,24 +40,27 @@ def kernel_hash() -> str:
 
 
 def algorithmic_bytes(res: dict, n: int, n_leaf: int, scaled: bool, local: bool) -> float:
-    """Bytes the trajectory kernel must move per launch for this data layout,
-    from the work counters (per-unit figures are listed in the design notes):
-      selection: 256 u16 leaves of one group (512 B) + 2 list pointers (16 B)
-      scanned entry at v or u: 4 B index + 2 B neighbour degree (+4 B scale
-        for the scaled proposal, charged on every scanned entry)
-      decrement: 2 B read + 2 B write; retiring v and u: 2 x 2 B
-      local-repair entry: 4 B index + 2 B degree + 4 B scale or stamp
+    """Bytes the trajectory kernel must move per launch for this data layout
+    (a lower bound: each access counted at its element size), from the work
+    counters; the per-unit figures are listed in the design notes:
+      per step: the selected vertex's leaf group (256 x u16 = 512 B), the two
+        list pointers of v and u (16 B), retiring v and u (2 x 2 B degree,
+        2 x 4 B scale when scaled)
+      scanned entry at v or u: 4 B index + 2 B neighbour degree, +4 B scale
+        when the proposal is scaled
+      degree decrement: 2 B read + 2 B write
+      local-repair entry (gathered or summed): 4 B index + 4 B scale/stamp
       local value: 8 B list pointers + 4 B old value + 4 B new value
-      trajectory init: degree template read + write (4 B per leaf),
-        r/c copy (16 B per row/column pair), stamp clear (8 B per row/column)
+      trajectory start: degree template read + write (4 B per leaf), scale
+        records (4 B read + 8 B write per vertex) when scaled
     """
     steps = res["n_steps"]
-    b = steps * (512 + 16 + 4)
+    b = steps * (512 + 16 + (12 if scaled else 4))
     b += res["n_entries_scanned"] * (10 if scaled else 6)
     b += res["n_decrements"] * 4
-    b += res["n_local_entries"] * 10
+    b += res["n_local_entries"] * 8
     b += res["n_local_values"] * 16
-    per_traj = 4 * n_leaf + (16 * n if scaled else 0) + (8 * n if local else 0)
+    per_traj = 4 * n_leaf + (24 * n if scaled else 0)
     b += res["n_traj"] * per_traj
     return float(b)
 
@@ -86,7 +89,21 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (to scale HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                                               "copies": 3}}), flush=True)
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; N > 1 is not supported "

@@ -168,6 +168,38 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count,
                        uint64_t *path_hash, int32_t *path, int32_t *counters,
                        void *stream);
 
+/* Create one handle holding `count` matrices (batching): matrix b is given
+ * by n[b], nnz[b], row_ptr[b], col_idx[b], col_ptr[b], row_idx[b] and
+ * values[b] (values may be NULL for all-0/1 input; a batch is all 0/1 or
+ * all weighted), each with the layout and checks of perm_est_create.
+ * Errors as perm_est_create; nothing is created if any matrix is invalid. */
+int perm_est_create_batch(int32_t count, const int32_t *n, const int64_t *nnz,
+                          const int32_t *const *row_ptr, const int32_t *const *col_idx,
+                          const int32_t *const *col_ptr, const int32_t *const *row_idx,
+                          const float *const *values, const perm_est_options *opts,
+                          perm_est_t **out);
+
+/* run flags */
+#define PE_RUN_AUTOTUNE 1  /* pick the launch shape (waves per block, blocks
+                              per CU) by timing candidates on a probe slice
+                              the first time a schedule kind is run; results
+                              do not depend on the shape                     */
+
+/* Run trajectories 0..n_traj[b]-1 of every matrix b of a batch handle in one
+ * persistent launch (Alg. 2 per trajectory, matrix b uses counter word b)
+ * and reduce each matrix separately.
+ *   n_traj:    host int64[count], each in [1, 2^32).
+ *   res:       host perm_est_result[count]; the work-unit fields and
+ *              `seconds` describe the whole launch.
+ *   logw, alive, path_hash: device arrays of sum(n_traj) entries (matrix b
+ *              at offset sum_{c<b} n_traj[c]), or NULL.
+ *   flags:     PE_RUN_AUTOTUNE or 0.
+ * Errors: PE_EINVAL, PE_ENOTSUP, PE_ENOMEM, PE_EDEVICE. */
+int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed,
+                       const perm_est_schedule *sched, perm_est_result *res,
+                       double *logw, uint8_t *alive, uint64_t *path_hash,
+                       int32_t flags, void *stream);
+
 /* Release every device and host resource of the handle (NULL is a no-op). */
 void perm_est_destroy(perm_est_t *h);
 

@@ -58,6 +58,8 @@ class _Sched(C.Structure):
         ("theta_tr", C.c_double),
         ("precision", C.c_int32),
         ("pad", C.c_int32),
+        ("model", C.c_void_p),
+        ("mix_alpha", C.c_double),
     ]
 
 
@@ -104,7 +106,9 @@ def _p(a: Optional[np.ndarray]):
 
 # ---------------------------------------------------------------- schedules
 VR_MD, VR_ROW = 0, 1
-SK_NONE, SK_FIXED, SK_ADAPTIVE, SK_LOCAL = 0, 1, 2, 3
+SK_NONE, SK_FIXED, SK_ADAPTIVE, SK_LOCAL, SK_LEARNED = 0, 1, 2, 3, 4
+MLP_IN, MLP_H = 8, 64
+MLP_NPARAM = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 DM_NONE, DM_ALL, DM_THRS, DM_TRCK = 0, 1, 2, 3
 CONTRACT, PAPER = 0, 1
 
@@ -120,13 +124,22 @@ class Schedule:
     theta_th: float = 0.33
     theta_tr: float = 0.33
     precision: int = CONTRACT
+    model: Optional[np.ndarray] = None   # quantised MLP parameters (float64, MLP_NPARAM)
+    mix_alpha: float = 0.05
 
     def c(self) -> _Sched:
+        if self.sk_policy == SK_LEARNED:
+            if self.model is None or self.model.size != MLP_NPARAM:
+                raise ValueError("the learned proposal needs a model of MLP_NPARAM parameters")
+            self._model_buf = np.ascontiguousarray(self.model, dtype=np.float64)
+            mp = self._model_buf.ctypes.data
+        else:
+            mp = None
         return _Sched(self.vertex_rule, self.sk_policy, self.dm_policy, self.initial_dm, self.K0,
-                      self.K, self.theta_th, self.theta_tr, self.precision, 0)
+                      self.K, self.theta_th, self.theta_tr, self.precision, 0, mp, self.mix_alpha)
 
     def replace(self, **kw) -> "Schedule":
-        d = dict(self.__dict__)
+        d = {k: v for k, v in self.__dict__.items() if not k.startswith("_")}
         d.update(kw)
         return Schedule(**d)
 
@@ -308,3 +321,36 @@ def ryser_f64(dense) -> float:
     if n == 0:
         return 1.0
     return float(lib().or_ryser_f64(n, _p(A)))
+
+
+def plog2(s: float) -> float:
+    lib().or_plog2.argtypes = [C.c_double]
+    lib().or_plog2.restype = C.c_double
+    return float(lib().or_plog2(s))
+
+
+def learned_logit(model: np.ndarray, x) -> int:
+    L = lib()
+    L.or_learned_logit.argtypes = [C.c_void_p, C.c_void_p]
+    L.or_learned_logit.restype = C.c_int32
+    m = np.ascontiguousarray(model, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    return int(L.or_learned_logit(m.ctypes.data, xx.ctypes.data))
+
+
+def learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row) -> np.ndarray:
+    L = lib()
+    L.or_learned_features.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                      C.c_int32, C.c_int32, C.c_void_p]
+    x = np.zeros(MLP_IN, dtype=np.float64)
+    L.or_learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row, x.ctypes.data)
+    return x
+
+
+def learned_weights(logits, alpha: float) -> np.ndarray:
+    L = lib()
+    L.or_learned_weights.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_void_p]
+    lg = np.ascontiguousarray(logits, dtype=np.int32)
+    w = np.zeros(lg.size, dtype=np.uint64)
+    L.or_learned_weights(lg.ctypes.data, lg.size, alpha, w.ctypes.data)
+    return w

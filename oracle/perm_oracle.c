@@ -73,10 +73,12 @@ typedef struct {
     double theta_th, theta_tr;
     int32_t precision;   /* 0 = CONTRACT (binary32 scaling), 1 = PAPER      */
     int32_t pad;
+    const double *model; /* learned proposal: quantised MLP parameters       */
+    double mix_alpha;    /* uniform share mixed into the learned proposal    */
 } or_sched;
 
 enum { VR_MD = 0, VR_ROW = 1 };
-enum { SK_NONE = 0, SK_FIXED = 1, SK_ADAPTIVE = 2, SK_LOCAL = 3 };
+enum { SK_NONE = 0, SK_FIXED = 1, SK_ADAPTIVE = 2, SK_LOCAL = 3, SK_LEARNED = 4 };
 enum { DM_NONE = 0, DM_ALL = 1, DM_THRS = 2, DM_TRCK = 3 };
 enum { PREC_CONTRACT = 0, PREC_PAPER = 1 };
 
@@ -476,6 +478,100 @@ int or_prep(const or_mat *A, int32_t initial_dm, int32_t K0, int32_t prec,
     return 1;
 }
 
+/* ------------------------------------------------- learned proposal */
+/* A small per-edge network replaces the scaling-based scores (no inner SK).
+ * Its inference is defined on fixed grids so that every sum is exact:
+ *   features x[0..7] of the candidate edge (rho = row end, gam = column
+ *   end) at step t:
+ *     x0 = min(deg rho, 255)/64, x1 = min(deg gam, 255)/64,
+ *     x2 = Q(plog2(r0[rho])/4), x3 = Q(plog2(c0[gam])/4), x4 = Q(t/n),
+ *     x5 = 1 if the selected vertex is a row, x6 = x7 = 0;
+ *   Q(y) = clamp(rint(64 y), -256, 255)/64; plog2(s) = e - 2 + 2m for
+ *   s = m 2^e, m in [0.5, 1) (piecewise-linear log2, exact);
+ *   h1 = A(x W1 + b1), h2 = A(h1 W2 + b2), L = Lq(h2 . w3 + b3) with
+ *   A(y) = clamp(rint(64 max(y, 0)), 0, 255)/64 and Lq(y) = clamp(rint(16 y),
+ *   -1024, 1023) (logit in units of 1/16); weights are multiples of 1/64.
+ * Softmax by the integer table E[d] = rint(2^24 exp(-d/16)), d = L_max - L_i,
+ * then w_i = max(1, rint(2^24 ((1 - a) E_i / sum E + a / k))).
+ * Parameter layout (doubles): W1[8][64], b1[64], W2[64][64], b2[64],
+ * w3[64], b3. */
+#define MLP_H 64
+#define MLP_IN 8
+#define MLP_NPARAM (MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+#define ETAB_N 2048
+
+static double q64(double y, double lo, double hi)
+{
+    double k = rint(y * 64.0);
+    if (k < lo) k = lo;
+    if (k > hi) k = hi;
+    return k / 64.0;
+}
+
+double or_plog2(double s)
+{
+    int e;
+    double m = frexp(s, &e);
+    return (double)e - 2.0 + 2.0 * m;
+}
+
+void or_learned_features(int32_t deg_rho, int32_t deg_gam, double r0_rho, double c0_gam,
+                         int32_t t, int32_t n, int32_t v_is_row, double *x)
+{
+    x[0] = (double)(deg_rho < 255 ? deg_rho : 255) / 64.0;
+    x[1] = (double)(deg_gam < 255 ? deg_gam : 255) / 64.0;
+    x[2] = q64(or_plog2(r0_rho) / 4.0, -256.0, 255.0);
+    x[3] = q64(or_plog2(c0_gam) / 4.0, -256.0, 255.0);
+    x[4] = q64((double)t / (double)n, -256.0, 255.0);
+    x[5] = v_is_row ? 1.0 : 0.0;
+    x[6] = 0.0;
+    x[7] = 0.0;
+}
+
+/* logit in units of 1/16 (exact grid arithmetic) */
+int32_t or_learned_logit(const double *P, const double *x)
+{
+    const double *W1 = P, *b1 = W1 + MLP_IN * MLP_H, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const double *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    double h1[MLP_H], h2[MLP_H];
+    for (int j = 0; j < MLP_H; ++j) {
+        double acc = b1[j];
+        for (int k = 0; k < MLP_IN; ++k) acc += x[k] * W1[k * MLP_H + j];
+        h1[j] = q64(acc > 0.0 ? acc : 0.0, 0.0, 255.0);
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double acc = b2[j];
+        for (int k = 0; k < MLP_H; ++k) acc += h1[k] * W2[k * MLP_H + j];
+        h2[j] = q64(acc > 0.0 ? acc : 0.0, 0.0, 255.0);
+    }
+    double acc = b3[0];
+    for (int k = 0; k < MLP_H; ++k) acc += h2[k] * w3[k];
+    double L = rint(acc * 16.0);
+    if (L < -1024.0) L = -1024.0;
+    if (L > 1023.0) L = 1023.0;
+    return (int32_t)L;
+}
+
+static int64_t etab(int32_t d)
+{
+    if (d >= ETAB_N) return 0;
+    return (int64_t)rint(16777216.0 * exp(-(double)d / 16.0));
+}
+
+/* integer weights of the learned proposal for k candidates with logits L */
+void or_learned_weights(const int32_t *L, int32_t k, double alpha, uint64_t *w)
+{
+    int32_t lmax = L[0];
+    for (int32_t a = 1; a < k; ++a) if (L[a] > lmax) lmax = L[a];
+    int64_t S = 0;
+    for (int32_t a = 0; a < k; ++a) S += etab(lmax - L[a]);
+    for (int32_t a = 0; a < k; ++a) {
+        double q = (1.0 - alpha) * (double)etab(lmax - L[a]) / (double)S + alpha / (double)k;
+        double r = rint(16777216.0 * q);
+        w[a] = r >= 1.0 ? (uint64_t)r : 1;
+    }
+}
+
 /* ---------------------------------------------------------- trajectory */
 typedef struct {
     uint8_t *act;      /* 2n */
@@ -485,6 +581,7 @@ typedef struct {
     int32_t *cand_v, *cand_e; /* candidate vertex / CSR edge */
     uint64_t *cand_w;
     double *cand_s;
+    int32_t *cand_L;   /* learned-proposal logits of the candidates */
     int32_t *nb_v;     /* N_t(v)\{u} (other candidates of v)  */
     int32_t *nb_u;     /* N_t(u)\{v} */
     uint8_t *mark_r, *mark_c;
@@ -569,6 +666,7 @@ static int tw_alloc(traj_work *w, const or_mat *A)
     w->cand_e = malloc(sizeof(int32_t) * N);
     w->cand_w = malloc(sizeof(uint64_t) * N);
     w->cand_s = malloc(sizeof(double) * N);
+    w->cand_L = malloc(sizeof(int32_t) * N);
     w->nb_v = malloc(sizeof(int32_t) * N);
     w->nb_u = malloc(sizeof(int32_t) * N);
     w->mark_r = calloc(N, 1);
@@ -577,7 +675,7 @@ static int tw_alloc(traj_work *w, const or_mat *A)
     w->list_c = malloc(sizeof(int32_t) * N);
     w->new_r = malloc(sizeof(double) * N);
     w->new_c = malloc(sizeof(double) * N);
-    if (!w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e ||
+    if (!w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e || !w->cand_L ||
         !w->cand_w || !w->cand_s || !w->nb_v || !w->nb_u || !w->mark_r || !w->mark_c ||
         !w->list_r || !w->list_c || !w->new_r || !w->new_c)
         return -1;
@@ -587,7 +685,7 @@ static int tw_alloc(traj_work *w, const or_mat *A)
 static void tw_free(traj_work *w)
 {
     free(w->act); free(w->deg); free(w->removed); free(w->r); free(w->c);
-    free(w->cand_v); free(w->cand_e); free(w->cand_w); free(w->cand_s);
+    free(w->cand_v); free(w->cand_e); free(w->cand_w); free(w->cand_s); free(w->cand_L);
     free(w->nb_v); free(w->nb_u); free(w->mark_r); free(w->mark_c);
     free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c);
     free(w->heap);
@@ -796,7 +894,18 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         int v_is_row = v < n;
         uint64_t W = 0;
         double S_paper = 0.0;
-        if (prec == PREC_CONTRACT) {
+        if (S->sk_policy == SK_LEARNED) {
+            int32_t *Lg = w->cand_L;
+            for (int32_t a = 0; a < kc; ++a) {
+                int32_t y = w->cand_v[a];
+                int32_t rho = v_is_row ? v : y, gam = v_is_row ? y : v;
+                double x[MLP_IN];
+                or_learned_features(w->deg[rho], w->deg[gam], r0[rho], c0[gam - n], t, n, v_is_row, x);
+                Lg[a] = or_learned_logit(S->model, x);
+            }
+            or_learned_weights(Lg, kc, S->mix_alpha, w->cand_w);
+            for (int32_t a = 0; a < kc; ++a) W += w->cand_w[a];
+        } else if (prec == PREC_CONTRACT) {
             float smax = 0.0f;
             float sv[1];
             (void)sv;
@@ -832,8 +941,8 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         if (pc && pc->stop_at == t) {
             for (int32_t a = 0; a < kc; ++a) {
                 pc->cand_out[a] = w->cand_v[a];
-                pc->prob_out[a] = (prec == PREC_CONTRACT) ? (double)w->cand_w[a] / (double)W
-                                                          : w->cand_s[a] / S_paper;
+                pc->prob_out[a] = (prec == PREC_CONTRACT || S->sk_policy == SK_LEARNED)
+                                      ? (double)w->cand_w[a] / (double)W : w->cand_s[a] / S_paper;
             }
             *pc->ncand_out = kc;
             *pc->stopped = 1;
@@ -850,7 +959,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
             if (pick < 0) { if (pc->stopped) *pc->stopped = -1; out->steps = t; return; }
         } else if (kc == 1) {
             pick = 0;
-        } else if (prec == PREC_CONTRACT) {
+        } else if (prec == PREC_CONTRACT || S->sk_policy == SK_LEARNED) {
             uint64_t j = or_uniform_below(seed, k, b, (uint32_t)t, 0, W);
             uint64_t pre = 0;
             pick = kc - 1;
@@ -867,7 +976,8 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
 
         /* ---- importance correction X <- X * B_{v,u} / q_t(u|v) */
         double factor;
-        if (prec == PREC_CONTRACT) factor = entry_d(A, e_vu) * ((double)W / (double)w->cand_w[pick]);
+        if (prec == PREC_CONTRACT || S->sk_policy == SK_LEARNED)
+            factor = entry_d(A, e_vu) * ((double)W / (double)w->cand_w[pick]);
         else factor = entry_d(A, e_vu) * (S_paper / w->cand_s[pick]);
         {
             int e2;
@@ -879,6 +989,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         int32_t rho = v_is_row ? v : u;
         int32_t gam = v_is_row ? u : v; /* vertex id n + j */
         double z = w->r[rho] * w->c[gam - n];
+        if (S->sk_policy == SK_LEARNED) z = (double)w->cand_w[pick] / (double)W;
 
         if (path) { path[2 * t] = v; path[2 * t + 1] = u; }
         h = or_splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);

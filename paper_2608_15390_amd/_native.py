@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpermest.so")
+# PERM_EST_LIBRARY selects another build of the same library (same ABI)
+LIB_PATH = os.environ.get("PERM_EST_LIBRARY") or os.path.join(_PKG, "libpermest.so")
 
 PE_OK, PE_EINVAL, PE_ENOMEM, PE_EDEVICE, PE_ENOTSUP = 0, -1, -2, -3, -4
 
@@ -62,12 +63,17 @@ class Result(C.Structure):
 
 EXPORTS = [
     "perm_est_create",
+    "perm_est_create_batch",
     "perm_est_schedule_preset",
     "perm_est_run",
     "perm_est_run_range",
+    "perm_est_run_batch",
     "perm_est_destroy",
     "perm_est_last_error",
 ]
+
+PE_FLAG_FORCE_HBM = 1
+PE_RUN_AUTOTUNE = 1
 
 _lib = None
 
@@ -91,6 +97,11 @@ def load():
     L.perm_est_run_range.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, C.POINTER(Schedule),
                                      C.POINTER(Result), P, P, P, P, P, P]
     L.perm_est_run_range.restype = C.c_int
+    PP = C.POINTER(C.c_void_p)
+    L.perm_est_create_batch.argtypes = [C.c_int32, P, P, PP, PP, PP, PP, PP, C.POINTER(Options), C.POINTER(P)]
+    L.perm_est_create_batch.restype = C.c_int
+    L.perm_est_run_batch.argtypes = [P, P, C.c_uint64, C.POINTER(Schedule), P, P, P, P, C.c_int32, P]
+    L.perm_est_run_batch.restype = C.c_int
     L.perm_est_destroy.argtypes = [P]
     L.perm_est_destroy.restype = None
     L.perm_est_last_error.argtypes = []

@@ -1,0 +1,336 @@
+// mlp.hpp -- the per-edge proposal network on matrix cores.
+//
+// Network: 8 edge features -> 64 (ReLU) -> 64 (ReLU) -> 1 logit.
+// Parameters (float, packed): W1[8][64], b1[64], W2[64][64], b2[64],
+// w3[64], b3.  Layers 1 and 2 run as bf16 MFMA 16x16x16 tiles over 16
+// records at a time with float accumulation; layer 3 is a 64-term dot
+// product reduced across lanes.
+//
+// MFMA 16x16x16 bf16 operand layout (one wave): for lane l, A[i][k] with
+// i = l % 16, k = 4 (l / 16) + j; B[k][c] with c = l % 16,
+// k = 4 (l / 16) + j; the result D[i][c] with c = l % 16, i = 4 (l / 16) + j
+// (j = 0..3).
+#pragma once
+#include "device.hpp"
+
+namespace pe {
+
+constexpr int kIn = 8, kH = 64;
+constexpr int kNParam = kIn * kH + kH + kH * kH + kH + kH + 1;  // 4801
+// offsets into the packed parameter vector
+constexpr int kOffW1 = 0, kOffB1 = kIn * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
+              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Weights in matrix-core form, staged once per block in LDS:
+//   w1[16][64] bf16 (rows 8..15 zero), w2[64][64] bf16, and float b1, b2, w3, b3.
+struct MlpLds {
+    short w1[16 * kH];
+    short w2[kH * kH];
+    float b1[kH], b2[kH], w3[kH];
+    float b3;
+};
+
+__device__ void stage_weights(MlpLds *s, const float *P) {
+    for (int i = threadIdx.x; i < 16 * kH; i += blockDim.x) {
+        const int k = i / kH, c = i % kH;
+        s->w1[i] = k < kIn ? to_bf16(P[kOffW1 + k * kH + c]) : (short)0;
+    }
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) s->w2[i] = to_bf16(P[kOffW2 + i]);
+    for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+        s->b1[i] = P[kOffB1 + i];
+        s->b2[i] = P[kOffB2 + i];
+        s->w3[i] = P[kOffW3 + i];
+    }
+    if (threadIdx.x == 0) s->b3 = P[kOffB3];
+}
+
+// Per-wave scratch for one 16-record tile: a [16][64] bf16 activation tile.
+struct TileLds {
+    short h[16 * kH];
+};
+
+// Forward of one tile.  `xa` is this lane's A operand of the feature tile
+// (record l % 16, features 4 (l / 16) .. +3; features 8..15 are zero).
+// QUANT: re-quantise the ReLU outputs onto the 1/64 grid [0, 255/64]
+// (inference); otherwise plain ReLU (training).  Outputs in D layout:
+// z1[nt], z2[nt] (pre-activations, column 16 nt + l % 16, rows
+// 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (valid in every lane).
+template <bool QUANT>
+__device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf16x4 xa, f32x4 z1[4],
+                                                 f32x4 z2[4], float logit[4]) {
+    const int l = lane_id();
+    const int c0 = l % 16, r0 = 4 * (l / 16);
+    auto act = [](float z) -> float {
+        float h = z > 0.0f ? z : 0.0f;
+        if (QUANT) {
+            float k = rintf(h * 64.0f);
+            k = k > 255.0f ? 255.0f : k;
+            h = k * (1.0f / 64.0f);
+        }
+        return h;
+    };
+    // layer 1: [16 x 16] x [16 x 64]
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        bf16x4 b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = W->w1[(r0 + j) * kH + 16 * nt + c0];
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma16(xa, b, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[j] = acc[j] + W->b1[16 * nt + c0];
+            T->h[(r0 + j) * kH + 16 * nt + c0] = to_bf16(act(acc[j]));
+        }
+        z1[nt] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // layer 2: [16 x 64] x [64 x 64], A read back from LDS in A layout
+    bf16x4 a2[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+        a2[ks] = *reinterpret_cast<const bf16x4 *>(&T->h[c0 * kH + 16 * ks + r0]);
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            bf16x4 b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = W->w2[(16 * ks + r0 + j) * kH + 16 * nt + c0];
+            acc = mfma16(a2[ks], b, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[j] = acc[j] + W->b2[16 * nt + c0];
+            part[j] = part[j] + act(acc[j]) * W->w3[16 * nt + c0];
+        }
+        z2[nt] = acc;
+    }
+    // layer 3: sum the 64 columns over the 16 lanes of each row group
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float v = part[j];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) v = v + __shfl_xor(v, o);
+        logit[j] = v + W->b3;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// ------------------------------------------------------------- training
+// Feature tile A operand for records [r, r + 16) of X[n][8] (zero past n)
+__device__ __forceinline__ bf16x4 load_x_tile(const float *X, int64_t n, int64_t r) {
+    const int l = lane_id();
+    const int64_t row = r + l % 16;
+    bf16x4 a;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * (l / 16) + j;
+        a[j] = (row < n && k < kIn) ? to_bf16(X[row * kIn + k]) : (short)0;
+    }
+    return a;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_forward(const float *P, const float *X, int64_t n, float *logits) {
+    __shared__ MlpLds W;
+    __shared__ TileLds tiles[4];
+    stage_weights(&W, P);
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, l = lane_id();
+    const int64_t tiles_total = (n + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles_total; t += (int64_t)gridDim.x * 4) {
+        f32x4 z1[4], z2[4];
+        float lg[4];
+        mlp_tile_forward<false>(&W, &tiles[wave], load_x_tile(X, n, 16 * t), z1, z2, lg);
+        if (l % 16 == 0)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = 16 * t + 4 * (l / 16) + j;
+                if (row < n) logits[row] = lg[j];
+            }
+    }
+}
+
+// per group: softmax, d loss / d logit = (softmax - target) / G, loss
+__global__ void k_softmax_xent(const float *logits, const float *targets, const int64_t *gstart,
+                               const int32_t *glen, int64_t g0, int64_t g1, int64_t G, float *dlogits,
+                               double *loss) {
+    const int64_t g = g0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= g1) return;
+    const int64_t s = gstart[g];
+    const int32_t k = glen[g];
+    float mx = -3.0e38f;
+    for (int32_t i = 0; i < k; ++i) mx = fmaxf(mx, logits[s + i]);
+    float sum = 0.0f;
+    for (int32_t i = 0; i < k; ++i) sum += expf(logits[s + i] - mx);
+    double lg = 0.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const float p = expf(logits[s + i] - mx) / sum;
+        const float y = targets[s + i];
+        dlogits[s + i] = (p - y) / (float)G;
+        if (y > 0.0f) lg -= (double)y * log((double)p > 1e-30 ? (double)p : 1e-30);
+    }
+    atomicAdd(loss, lg / (double)G);
+}
+
+// Backward over records [r0, r1): gradients of all parameters, accumulated
+// per wave in registers and added to grad[] once.
+__global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const float *X, const float *dlogits,
+                                                      int64_t r0, int64_t r1, float *grad) {
+    __shared__ MlpLds W;
+    __shared__ TileLds tiles[4];
+    stage_weights(&W, P);
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, l = lane_id();
+    const int c0 = l % 16, q0 = 4 * (l / 16);
+    TileLds *T = &tiles[wave];
+    f32x4 gW2[4][4], gW1[4];
+    float gb1[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0}, gw3[4] = {0, 0, 0, 0}, gb3 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = f32x4{0, 0, 0, 0};
+    }
+    const int64_t n = r1 - r0;
+    const int64_t tiles_total = (n + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles_total; t += (int64_t)gridDim.x * 4) {
+        const int64_t base = r0 + 16 * t;
+        f32x4 z1[4], z2[4];
+        float lg[4];
+        mlp_tile_forward<false>(&W, T, load_x_tile(X, r1, base), z1, z2, lg);
+        float dl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t row = base + q0 + j;
+            dl[j] = row < r1 ? dlogits[row] : 0.0f;
+            if (c0 == 0) gb3 += dl[j];
+        }
+        // dZ2 = dl w3 1[z2 > 0]; gradients of w3, b2; dW2 = H1^T dZ2
+        f32x4 dz2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const float w3c = W.w3[16 * nt + c0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float h2 = z2[nt][j] > 0.0f ? z2[nt][j] : 0.0f;
+                gw3[nt] += h2 * dl[j];
+                dz2[nt][j] = z2[nt][j] > 0.0f ? dl[j] * w3c : 0.0f;
+                gb2[nt] += dz2[nt][j];
+            }
+        }
+        bf16x4 h1a[4], dz2b[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h1a[nt][j] = T->h[(q0 + j) * kH + 16 * nt + c0];  // H1 in D layout = A of H1^T
+                dz2b[nt][j] = to_bf16(dz2[nt][j]);
+            }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) gW2[mt][nt] = mfma16(h1a[mt], dz2b[nt], gW2[mt][nt]);
+        // dH1 = dZ2 W2^T: dZ2 to A layout through LDS
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) T->h[(q0 + j) * kH + 16 * nt + c0] = dz2b[nt][j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        bf16x4 dza[4];
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs) dza[cs] = *reinterpret_cast<const bf16x4 *>(&T->h[c0 * kH + 16 * cs + q0]);
+        bf16x4 dz1b[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int cs = 0; cs < 4; ++cs) {
+                bf16x4 b;  // B[c][k] = W2[k][c], k = 16 nt + c0, c = 16 cs + q0 + j
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = W.w2[(16 * nt + c0) * kH + 16 * cs + q0 + j];
+                acc = mfma16(dza[cs], b, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float d = z1[nt][j] > 0.0f ? acc[j] : 0.0f;
+                gb1[nt] += d;
+                dz1b[nt][j] = to_bf16(d);
+            }
+        }
+        // dW1 = X^T dZ1 (A[k][i] = X[base + i][k], rows k >= 8 zero)
+        bf16x4 xt;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t row = base + q0 + j;
+            xt[j] = (row < r1 && c0 < kIn) ? to_bf16(X[row * kIn + c0]) : (short)0;
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) gW1[nt] = mfma16(xt, dz1b[nt], gW1[nt]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+    // fold the per-lane partial sums into grad[]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                atomicAdd(&grad[kOffW2 + (16 * mt + q0 + j) * kH + 16 * nt + c0], gW2[mt][nt][j]);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (q0 + j < kIn) atomicAdd(&grad[kOffW1 + (q0 + j) * kH + 16 * nt + c0], gW1[nt][j]);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        float a = gb1[nt], b = gb2[nt], c = gw3[nt];
+        a += __shfl_xor(a, 16); a += __shfl_xor(a, 32);
+        b += __shfl_xor(b, 16); b += __shfl_xor(b, 32);
+        c += __shfl_xor(c, 16); c += __shfl_xor(c, 32);
+        if (l < 16) {
+            atomicAdd(&grad[kOffB1 + 16 * nt + c0], a);
+            atomicAdd(&grad[kOffB2 + 16 * nt + c0], b);
+            atomicAdd(&grad[kOffW3 + 16 * nt + c0], c);
+        }
+    }
+    float s3 = gb3;
+    for (int o = 32; o > 0; o >>= 1) s3 += __shfl_xor(s3, o);
+    if (l == 0) atomicAdd(&grad[kOffB3], s3);
+}
+
+__global__ void k_adam(float *P, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    m[i] = b1 * m[i] + (1.0f - b1) * gi;
+    v[i] = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mh = m[i] / c1, vh = v[i] / c2;
+    P[i] = P[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_fill_f32n(int64_t n, float *p, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace pe

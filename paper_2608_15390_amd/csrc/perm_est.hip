@@ -80,11 +80,8 @@ struct Prepared {
     }
 };
 
-}  // namespace
-
-struct perm_est {
-    int device = 0;
-    uint32_t opt_flags = 0;
+// one input matrix on the device, plus its preprocessed variants
+struct MatData {
     int32_t n = 0;
     int64_t m = 0;
     bool weighted = false;
@@ -93,20 +90,53 @@ struct perm_est {
             *csc2csr = nullptr, *edge_row = nullptr;
     float *val = nullptr, *val_csc = nullptr;
     std::vector<Prepared> preps;
+    int32_t *flags = nullptr;  // borrowed: the handle's small scratch integers
+
+    void release() {
+        for (auto &P : preps) P.release();
+        preps.clear();
+        dfree(row_ptr); dfree(col_idx); dfree(col_ptr); dfree(row_idx); dfree(csc2csr);
+        dfree(edge_row); dfree(val); dfree(val_csc);
+    }
+};
+
+// launch shape chosen for a (schedule, tier) pair
+struct Tune {
+    int32_t sk = -1, dm = -1, force_hbm = -1;
+    int32_t wpb = 4;      // waves per block
+    int32_t per_cu = 4;   // blocks per CU in the persistent grid
+};
+
+}  // namespace
+
+struct perm_est {
+    int device = 0;
+    uint32_t opt_flags = 0;
     int cu_count = 256;
+    std::vector<MatData> mats;
+    std::vector<Tune> tunes;
     // reusable run buffers
     char *hbm_state = nullptr;
     size_t hbm_bytes = 0;
-    uint32_t *work = nullptr;
+    uint32_t *work = nullptr;  // [0] item counter, [1] error bits
     unsigned long long *work_totals = nullptr;
-    DevStats *stats = nullptr;
-    int64_t *seg = nullptr;
     int32_t *flags = nullptr;  // small scratch integers for preprocessing loops
+    TrajArgs *args_dev = nullptr;
+    BatchArgs *batch_dev = nullptr;
+    int32_t *order_dev = nullptr;
+    int64_t *item_off_dev = nullptr, *seg_dev = nullptr;
+    DevStats *stats = nullptr;
+    size_t cap_mats = 0;
     double *tmp_logw = nullptr;
     uint8_t *tmp_alive = nullptr;
     int32_t *tmp_counters = nullptr;
     int64_t tmp_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // host copies the async uploads read from
+    std::vector<TrajArgs> args_host;
+    BatchArgs batch_host{};
+    std::vector<int32_t> order_host;
+    std::vector<int64_t> item_off_host, seg_host;
 };
 
 namespace {
@@ -144,7 +174,7 @@ int zero_flag(int32_t *dflag, hipStream_t s) {
 // rounds plus multi-source BFS augmentation, strongly connected components
 // of the contracted alternating digraph by trimming and max-label colouring,
 // then keep[e].  Returns ok = 0 when no perfect matching exists.
-int initial_filter(perm_est *h, uint8_t *keep, int32_t *ok, int32_t *out_mate_r, int32_t *out_mate_c,
+int initial_filter(MatData *h, uint8_t *keep, int32_t *ok, int32_t *out_mate_r, int32_t *out_mate_c,
                    hipStream_t s) {
     const int32_t n = h->n;
     int32_t *mate_r, *mate_c, *root, *level, *claim, *path_end, *scc, *color, *mark;
@@ -231,7 +261,7 @@ int initial_filter(perm_est *h, uint8_t *keep, int32_t *ok, int32_t *out_mate_r,
     return rc;
 }
 
-int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, Prepared &P) {
+int build_prepared(MatData *h, int32_t initial_dm, int32_t K0, hipStream_t s, Prepared &P) {
     const int32_t n = h->n;
     int rc;
     P.initial_dm = initial_dm;
@@ -333,7 +363,7 @@ int build_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, P
     return PE_OK;
 }
 
-int get_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, Prepared **out) {
+int get_prepared(MatData *h, int32_t initial_dm, int32_t K0, hipStream_t s, Prepared **out) {
     for (auto &P : h->preps)
         if (P.initial_dm == initial_dm && P.K0 == K0) { *out = &P; return PE_OK; }
     Prepared P;
@@ -347,25 +377,25 @@ int get_prepared(perm_est *h, int32_t initial_dm, int32_t K0, hipStream_t s, Pre
 uint32_t align_up(uint64_t x, uint64_t a) { return (uint32_t)((x + a - 1) / a * a); }
 
 template <int SK, bool DM>
-void launch_w(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s, const TrajArgs &a) {
-    if (wt) traj_kernel<SK, DM, true><<<blocks, threads, shmem, s>>>(a);
-    else traj_kernel<SK, DM, false><<<blocks, threads, shmem, s>>>(a);
+void launch_w(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s, const BatchArgs *b) {
+    if (wt) traj_kernel<SK, DM, true><<<blocks, threads, shmem, s>>>(b);
+    else traj_kernel<SK, DM, false><<<blocks, threads, shmem, s>>>(b);
 }
 
 template <int SK>
 void launch_dm(bool dm, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
-               const TrajArgs &a) {
-    if (dm) launch_w<SK, true>(wt, blocks, threads, shmem, s, a);
-    else launch_w<SK, false>(wt, blocks, threads, shmem, s, a);
+               const BatchArgs *b) {
+    if (dm) launch_w<SK, true>(wt, blocks, threads, shmem, s, b);
+    else launch_w<SK, false>(wt, blocks, threads, shmem, s, b);
 }
 
 void launch_traj(int sk, bool dm, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
-                 const TrajArgs &a) {
+                 const BatchArgs *b) {
     switch (sk) {
-        case PE_SK_NONE: launch_dm<kSkNone>(dm, wt, blocks, threads, shmem, s, a); break;
-        case PE_SK_FIXED: launch_dm<kSkFixed>(dm, wt, blocks, threads, shmem, s, a); break;
-        case PE_SK_ADAPTIVE: launch_dm<kSkAdaptive>(dm, wt, blocks, threads, shmem, s, a); break;
-        default: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, a); break;
+        case PE_SK_NONE: launch_dm<kSkNone>(dm, wt, blocks, threads, shmem, s, b); break;
+        case PE_SK_FIXED: launch_dm<kSkFixed>(dm, wt, blocks, threads, shmem, s, b); break;
+        case PE_SK_ADAPTIVE: launch_dm<kSkAdaptive>(dm, wt, blocks, threads, shmem, s, b); break;
+        default: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, b); break;
     }
 }
 
@@ -379,6 +409,345 @@ int check_schedule(const perm_est_schedule *s) {
     if (!std::isfinite(s->theta_th) || !std::isfinite(s->theta_tr)) return fail(PE_EINVAL, "bad thresholds");
     for (int i = 0; i < 4; ++i)
         if (s->reserved[i] != 0) return fail(PE_EINVAL, "reserved schedule fields must be 0");
+    return PE_OK;
+}
+
+// validate one CSR/CSC pair on the host and move it to the device
+int make_matrix(perm_est *h, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                const int32_t *col_ptr, const int32_t *row_idx, const float *values, MatData &M) {
+    if (n <= 0) return fail(PE_EINVAL, "n must be positive");
+    if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(PE_EINVAL, "nnz out of range");
+    if (nnz > 0 && (!col_idx || !row_idx)) return fail(PE_EINVAL, "null index array");
+    int rc;
+    if ((rc = check_lists(n, nnz, row_ptr, col_idx, "CSR"))) return rc;
+    if ((rc = check_lists(n, nnz, col_ptr, row_idx, "CSC"))) return rc;
+    if (values)
+        for (int64_t p = 0; p < nnz; ++p)
+            if (!(values[p] > 0.0f) || !std::isfinite(values[p]))
+                return fail(PE_EINVAL, "values must be finite and > 0");
+    M.n = n;
+    M.m = nnz;
+    M.weighted = values != nullptr;
+    M.flags = h->flags;
+    int32_t dm = 1;
+    for (int32_t a = 0; a < n; ++a) dm = std::max({dm, row_ptr[a + 1] - row_ptr[a], col_ptr[a + 1] - col_ptr[a]});
+    M.dmax = dm;
+    if ((rc = dalloc(&M.row_ptr, n + 1)) || (rc = dalloc(&M.col_ptr, n + 1)) || (rc = dalloc(&M.col_idx, nnz)) ||
+        (rc = dalloc(&M.row_idx, nnz)) || (rc = dalloc(&M.csc2csr, nnz)) || (rc = dalloc(&M.edge_row, nnz)))
+        return rc;
+    if (values && ((rc = dalloc(&M.val, nnz)) || (rc = dalloc(&M.val_csc, nnz)))) return rc;
+    auto up = [&](void *d, const void *src, size_t bytes) {
+        return bytes == 0 || hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(M.row_ptr, row_ptr, sizeof(int32_t) * (n + 1)) || !up(M.col_ptr, col_ptr, sizeof(int32_t) * (n + 1)) ||
+        !up(M.col_idx, col_idx, sizeof(int32_t) * nnz) || !up(M.row_idx, row_idx, sizeof(int32_t) * nnz) ||
+        (values && !up(M.val, values, sizeof(float) * nnz)))
+        return fail(PE_EDEVICE, "upload failed");
+    int32_t err = 0;
+    if (hipMemset(h->flags, 0, sizeof(int32_t)) != hipSuccess) return fail(PE_EDEVICE, "hipMemset failed");
+    k_csc2csr<<<blocks_for(n), 256>>>(n, M.row_ptr, M.col_idx, M.col_ptr, M.row_idx, M.csc2csr, h->flags);
+    k_edge_row<<<blocks_for(n), 256>>>(n, M.row_ptr, M.edge_row);
+    if (values) k_gather_f32<<<blocks_for(nnz), 256>>>(nnz, M.val, M.csc2csr, M.val_csc);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(&err, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(PE_EDEVICE, "edge map kernel failed");
+    if (err) return fail(PE_EINVAL, "CSR and CSC hold different entries");
+    return PE_OK;
+}
+
+int new_handle(const perm_est_options *opts, perm_est **out) {
+    if (opts && (opts->flags & ~PE_FLAG_FORCE_HBM) != 0) return fail(PE_EINVAL, "unknown option flags");
+    perm_est *h = new (std::nothrow) perm_est();
+    if (!h) return fail(PE_ENOMEM, "host allocation failed");
+    h->device = opts ? opts->device : 0;
+    h->opt_flags = opts ? opts->flags : 0;
+    *out = h;
+    if (hipSetDevice(h->device) != hipSuccess) return fail(PE_EDEVICE, "hipSetDevice failed");
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+        h->cu_count = cus;
+    int rc;
+    if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, 5)) || (rc = dalloc(&h->flags, 8)) ||
+        (rc = dalloc(&h->batch_dev, 1)))
+        return rc;
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+        return fail(PE_EDEVICE, "hipEventCreate failed");
+    return PE_OK;
+}
+
+// outputs of one matrix's share of a launch
+struct RunPart {
+    int64_t first = 0, count = 0;
+    double *logw = nullptr;
+    uint8_t *alive = nullptr;
+    uint64_t *path_hash = nullptr;
+    int32_t *path = nullptr;
+    int32_t *counters = nullptr;
+};
+
+int grow_tmp(perm_est *h, int64_t total) {
+    if (h->tmp_cap >= total) return PE_OK;
+    dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
+    h->tmp_cap = 0;
+    int rc;
+    if ((rc = dalloc(&h->tmp_logw, total)) || (rc = dalloc(&h->tmp_alive, total)) ||
+        (rc = dalloc(&h->tmp_counters, 4 * total)))
+        return rc;
+    h->tmp_cap = total;
+    return PE_OK;
+}
+
+int grow_mats(perm_est *h, size_t count) {
+    if (h->cap_mats >= count) return PE_OK;
+    dfree(h->args_dev); dfree(h->order_dev); dfree(h->item_off_dev); dfree(h->seg_dev); dfree(h->stats);
+    h->cap_mats = 0;
+    int rc;
+    if ((rc = dalloc(&h->args_dev, count)) || (rc = dalloc(&h->order_dev, count)) ||
+        (rc = dalloc(&h->item_off_dev, count + 1)) || (rc = dalloc(&h->seg_dev, 2 * count)) ||
+        (rc = dalloc(&h->stats, count)))
+        return rc;
+    h->cap_mats = count;
+    return PE_OK;
+}
+
+// one persistent launch over every matrix's trajectories + per-matrix
+// reductions.  tune_only: time the launch shape (wpb, per_cu) instead of
+// producing results (outputs go to scratch buffers).
+int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vector<RunPart> &parts,
+           perm_est_result *res, hipStream_t s, int wpb_req, int per_cu_req, double *elapsed_ms) {
+    const size_t count = h->mats.size();
+    int rc;
+    if ((rc = grow_mats(h, count))) return rc;
+    const bool own_rc = sched->sk_policy != PE_SK_NONE;
+    const bool local = sched->sk_policy == PE_SK_LOCAL;
+    const bool dm = sched->dm_policy != PE_DM_NONE;
+    const bool wt = h->mats[0].weighted;
+    for (auto &M : h->mats)
+        if (M.weighted != wt) return fail(PE_EINVAL, "a batch must be all 0/1 or all weighted");
+
+    // ---- per-matrix preprocessing and state layout (slots sized for the largest)
+    std::vector<Prepared *> prep(count);
+    int64_t total = 0;
+    uint64_t state_bytes = 0;
+    int32_t tree_total = 0;
+    for (size_t b = 0; b < count; ++b) {
+        if ((rc = get_prepared(&h->mats[b], sched->initial_dm, sched->K0, s, &prep[b]))) return rc;
+        total += parts[b].count;
+        tree_total = std::max(tree_total, prep[b]->tree.total);
+    }
+    if (total > ((int64_t)1 << 32) - 1) return fail(PE_EINVAL, "too many trajectories in one launch");
+    bool need_tmp = false;
+    for (auto &pt : parts) need_tmp = need_tmp || !pt.logw || !pt.alive || !pt.counters;
+    if (need_tmp && (rc = grow_tmp(h, total))) return rc;
+
+    h->args_host.assign(count, TrajArgs{});
+    int64_t tmp_off = 0;
+    for (size_t b = 0; b < count; ++b) {
+        const MatData &M = h->mats[b];
+        const Prepared *P = prep[b];
+        const int32_t n = M.n;
+        StateLayout L{};
+        uint64_t o = 0;
+        auto take = [&](uint64_t bytes) {
+            const uint64_t at = (o + 15) / 16 * 16;
+            o = at + bytes;
+            return (uint32_t)at;
+        };
+        L.deg = take((uint64_t)P->n_leaf * 2);
+        L.rec = take(own_rc ? 16ull * n : 0);
+        L.lst_a = take(4ull * P->dmax);
+        L.lst_b = take(4ull * P->dmax);
+        L.loc_r = take(local ? 4ull * n : 0);
+        L.loc_c = take(local ? 4ull * n : 0);
+        L.new_v = take(local ? 8ull * n : 0);
+        L.rem = take(dm ? 4ull * ((P->m + 31) / 32) : 0);
+        L.mate_r = take(dm ? 4ull * n : 0);
+        L.mate_c = take(dm ? 4ull * n : 0);
+        L.ws = take(dm ? 24ull * n : 0);
+        L.bytes = (uint32_t)((o + 255) / 256 * 256);
+        if (o >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
+        state_bytes = std::max<uint64_t>(state_bytes, L.bytes);
+
+        TrajArgs &a = h->args_host[b];
+        a.A = DevMat{n, (int32_t)P->m, P->row_ptr, P->col_idx, P->col_ptr, P->row_idx, P->csc2csr,
+                     P->edge_row, P->val, P->val_csc};
+        a.r0 = P->r0;
+        a.c0 = P->c0;
+        a.deg0 = P->deg0;
+        a.tree0 = P->tree0;
+        a.mate0_r = P->mate_r;
+        a.mate0_c = P->mate_c;
+        a.n_leaf = P->n_leaf;
+        a.tree = P->tree;
+        a.st = L;
+        a.ok0 = P->ok;
+        a.vertex_rule = sched->vertex_rule;
+        a.sk_policy = sched->sk_policy;
+        a.dm_policy = sched->dm_policy;
+        a.K = sched->K;
+        a.scaled = (P->r0 != nullptr) || own_rc;
+        a.theta_th = sched->theta_th;
+        a.theta_tr = sched->theta_tr;
+        a.seed = seed;
+        a.b = (uint32_t)b;
+        a.first = parts[b].first;
+        a.count = parts[b].count;
+        a.logw = parts[b].logw ? parts[b].logw : h->tmp_logw + tmp_off;
+        a.alive = parts[b].alive ? parts[b].alive : h->tmp_alive + tmp_off;
+        a.counters = parts[b].counters ? parts[b].counters : h->tmp_counters + 4 * tmp_off;
+        a.path_hash = parts[b].path_hash;
+        a.path = parts[b].path;
+        a.err = h->work + 1;
+        tmp_off += parts[b].count;
+    }
+    // processing order: most expensive matrices first (n * m per trajectory)
+    h->order_host.resize(count);
+    for (size_t b = 0; b < count; ++b) h->order_host[b] = (int32_t)b;
+    std::stable_sort(h->order_host.begin(), h->order_host.end(), [&](int32_t x, int32_t y) {
+        return (double)prep[x]->m * h->mats[x].n > (double)prep[y]->m * h->mats[y].n;
+    });
+    h->item_off_host.assign(count + 1, 0);
+    for (size_t i = 0; i < count; ++i) h->item_off_host[i + 1] = h->item_off_host[i] + parts[h->order_host[i]].count;
+    // each matrix reduces its own slice: segment (0, count_b) per matrix
+    h->seg_host.assign(2 * count, 0);
+    for (size_t b = 0; b < count; ++b) h->seg_host[2 * b + 1] = parts[b].count;
+
+    // ---- tier and launch shape
+    const size_t tree_bytes = (size_t)tree_total * 4;
+    const size_t kLdsBlock = 64 * 1024, kLdsCU = 160 * 1024;
+    const bool lds = tree_bytes + state_bytes <= 32 * 1024 && !(h->opt_flags & PE_FLAG_FORCE_HBM);
+    BatchArgs &B = h->batch_host;
+    B = BatchArgs{};
+    B.mats = h->args_dev;
+    B.order = h->order_dev;
+    B.item_off = h->item_off_dev;
+    B.count = (int32_t)count;
+    B.total = total;
+    B.work_next = h->work;
+    B.work_totals = h->work_totals;
+    B.lds_tree_bytes = (int32_t)tree_bytes;
+    int wpb = wpb_req > 0 ? wpb_req : 4;
+    size_t per_wave = tree_bytes + (lds ? state_bytes : 0);
+    wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, kLdsBlock / std::max<size_t>(per_wave, 1)));
+    const size_t shmem = (size_t)wpb * per_wave;
+    size_t per_cu = per_cu_req > 0 ? (size_t)per_cu_req : std::max<size_t>(1, 16 / wpb);
+    per_cu = std::max<size_t>(1, std::min<size_t>(per_cu, kLdsCU / std::max<size_t>(shmem, 1)));
+    const unsigned blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((total + wpb - 1) / wpb, (int64_t)h->cu_count * (int64_t)per_cu));
+    B.waves_per_block = wpb;
+    if (lds) {
+        B.hbm_state = nullptr;
+        B.lds_state_bytes = (int32_t)state_bytes;
+    } else {
+        const size_t need = (size_t)blocks * wpb * state_bytes;
+        if (h->hbm_bytes < need) {
+            dfree(h->hbm_state);
+            h->hbm_bytes = 0;
+            if ((rc = dalloc(&h->hbm_state, need))) return rc;
+            h->hbm_bytes = need;
+        }
+        B.hbm_state = h->hbm_state;
+        B.hbm_stride = state_bytes;
+        B.lds_state_bytes = 0;
+    }
+
+    PE_HIP(hipMemcpyAsync(h->args_dev, h->args_host.data(), sizeof(TrajArgs) * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(h->order_dev, h->order_host.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(h->item_off_dev, h->item_off_host.data(), sizeof(int64_t) * (count + 1),
+                          hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(h->seg_dev, h->seg_host.data(), sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(h->batch_dev, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
+    k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
+    k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
+    k_fill_i32<<<1, 64, 0, s>>>(10, reinterpret_cast<int32_t *>(h->work_totals), 0);
+    PE_HIP(hipEventRecord(h->ev0, s));
+    launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, s, h->batch_dev);
+    PE_HIP(hipGetLastError());
+    if (res) {
+        // per-matrix statistics over each matrix's slice of the outputs
+        for (size_t b = 0; b < count; ++b) {
+            const TrajArgs &a = h->args_host[b];
+            k_reduce_stats<<<1, 1024, 0, s>>>(a.logw, a.alive, a.counters, h->seg_dev + 2 * b, h->stats + b);
+        }
+        PE_HIP(hipGetLastError());
+    }
+    PE_HIP(hipEventRecord(h->ev1, s));
+    std::vector<DevStats> st(count);
+    uint32_t err_bits = 0;
+    unsigned long long wt_tot[5];
+    if (res) PE_HIP(hipMemcpyAsync(st.data(), h->stats, sizeof(DevStats) * count, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(wt_tot, h->work_totals, sizeof(wt_tot), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    PE_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (elapsed_ms) *elapsed_ms = ms;
+    if (err_bits)
+        return fail(PE_EDEVICE, "trajectory kernel reported an internal inconsistency (bits " +
+                                    std::to_string(err_bits) + ")");
+    if (res) {
+        for (size_t b = 0; b < count; ++b) {
+            perm_est_result &r = res[b];
+            r.log_estimate = st[b].log_estimate;
+            r.p_match = st[b].p_match;
+            r.rel_spread = st[b].rel_spread;
+            r.rse = st[b].rse;
+            r.ess = st[b].ess;
+            r.var_logw = st[b].var_logw;
+            r.max_logw = st[b].max_logw;
+            r.n_traj = st[b].n_traj;
+            r.n_alive = st[b].n_alive;
+            r.n_dm = st[b].n_dm;
+            r.n_full_sk = st[b].n_full_sk;
+            r.n_local_sk = st[b].n_local_sk;
+            r.n_steps = st[b].n_steps;
+            r.seconds = ms * 1e-3;  // the whole launch
+            // work units are per launch; reported on every matrix of the batch
+            r.n_entries_scanned = (int64_t)wt_tot[0];
+            r.n_decrements = (int64_t)wt_tot[1];
+            r.n_local_entries = (int64_t)wt_tot[2];
+            r.n_local_values = (int64_t)wt_tot[3];
+        }
+    }
+    return PE_OK;
+}
+
+// Launch-shape autotuner: time candidate (waves per block, blocks per CU)
+// pairs on a probe range of trajectories (results are identical for every
+// shape) and keep the fastest per (schedule kind, tier).
+int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, const std::vector<RunPart> &parts,
+                hipStream_t s, int *wpb, int *per_cu) {
+    const int force = (h->opt_flags & PE_FLAG_FORCE_HBM) ? 1 : 0;
+    for (auto &t : h->tunes)
+        if (t.sk == sched->sk_policy && t.dm == (sched->dm_policy != 0) && t.force_hbm == force) {
+            *wpb = t.wpb; *per_cu = t.per_cu;
+            return PE_OK;
+        }
+    // probe: a slice of every matrix (at least a few waves' worth per CU)
+    std::vector<RunPart> probe(parts.size());
+    int64_t total = 0;
+    for (auto &p : parts) total += p.count;
+    const int64_t want = std::min<int64_t>(total, (int64_t)h->cu_count * 16);
+    for (size_t b = 0; b < parts.size(); ++b) {
+        probe[b].first = parts[b].first;
+        probe[b].count = std::max<int64_t>(1, parts[b].count * want / std::max<int64_t>(total, 1));
+    }
+    const int cand_wpb[] = {1, 2, 4};
+    const int cand_cu[] = {4, 8, 16};
+    double best = 1e300;
+    Tune tb;
+    tb.sk = sched->sk_policy; tb.dm = sched->dm_policy != 0; tb.force_hbm = force;
+    for (int w : cand_wpb)
+        for (int c : cand_cu) {
+            const int per_cu_blocks = std::max(1, c / w);
+            double ms = 0;
+            int rc = launch(h, sched, seed, probe, nullptr, s, w, per_cu_blocks, &ms);
+            if (rc) return rc;
+            if (ms < best) { best = ms; tb.wpb = w; tb.per_cu = per_cu_blocks; }
+        }
+    h->tunes.push_back(tb);
+    *wpb = tb.wpb;
+    *per_cu = tb.per_cu;
     return PE_OK;
 }
 
@@ -425,56 +794,43 @@ int perm_est_schedule_preset(const char *name, perm_est_schedule *out) {
 int perm_est_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                     const int32_t *col_ptr, const int32_t *row_idx, const float *values,
                     const perm_est_options *opts, perm_est_t **out) {
+    const int32_t nn[1] = {n};
+    const int64_t zz[1] = {nnz};
+    return perm_est_create_batch(1, nn, zz, &row_ptr, &col_idx, &col_ptr, &row_idx, values ? &values : nullptr,
+                                 opts, out);
+}
+
+int perm_est_create_batch(int32_t count, const int32_t *n, const int64_t *nnz,
+                          const int32_t *const *row_ptr, const int32_t *const *col_idx,
+                          const int32_t *const *col_ptr, const int32_t *const *row_idx,
+                          const float *const *values, const perm_est_options *opts, perm_est_t **out) {
     if (!out) return fail(PE_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n <= 0) return fail(PE_EINVAL, "n must be positive");
-    if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(PE_EINVAL, "nnz out of range");
-    if (nnz > 0 && (!col_idx || !row_idx)) return fail(PE_EINVAL, "null index array");
-    if (opts && (opts->flags & ~PE_FLAG_FORCE_HBM) != 0) return fail(PE_EINVAL, "unknown option flags");
-    int rc;
-    if ((rc = check_lists(n, nnz, row_ptr, col_idx, "CSR"))) return rc;
-    if ((rc = check_lists(n, nnz, col_ptr, row_idx, "CSC"))) return rc;
-    if (values)
-        for (int64_t p = 0; p < nnz; ++p)
-            if (!(values[p] > 0.0f) || !std::isfinite(values[p])) return fail(PE_EINVAL, "values must be finite and > 0");
-    perm_est *h = new (std::nothrow) perm_est();
-    if (!h) return fail(PE_ENOMEM, "host allocation failed");
-    h->device = opts ? opts->device : 0;
-    h->opt_flags = opts ? opts->flags : 0;
-    h->n = n;
-    h->m = nnz;
-    h->weighted = values != nullptr;
-    int32_t dm = 1;
-    for (int32_t a = 0; a < n; ++a) dm = std::max({dm, row_ptr[a + 1] - row_ptr[a], col_ptr[a + 1] - col_ptr[a]});
-    h->dmax = dm;
-    auto bail = [&](int code) { perm_est_destroy(h); return code; };
-    if (hipSetDevice(h->device) != hipSuccess) return bail(fail(PE_EDEVICE, "hipSetDevice failed"));
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
-        h->cu_count = cus;
-    if ((rc = dalloc(&h->row_ptr, n + 1)) || (rc = dalloc(&h->col_ptr, n + 1)) ||
-        (rc = dalloc(&h->col_idx, nnz)) || (rc = dalloc(&h->row_idx, nnz)) ||
-        (rc = dalloc(&h->csc2csr, nnz)) || (rc = dalloc(&h->edge_row, nnz)) || (rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, 5)) || (rc = dalloc(&h->stats, 1)) ||
-        (rc = dalloc(&h->seg, 2)) || (rc = dalloc(&h->flags, 8)))
-        return bail(rc);
-    if (values && ((rc = dalloc(&h->val, nnz)) || (rc = dalloc(&h->val_csc, nnz)))) return bail(rc);
-    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
-        return bail(fail(PE_EDEVICE, "hipEventCreate failed"));
-    auto up = [&](void *d, const void *s, size_t bytes) {
-        return bytes == 0 || hipMemcpy(d, s, bytes, hipMemcpyHostToDevice) == hipSuccess;
-    };
-    if (!up(h->row_ptr, row_ptr, sizeof(int32_t) * (n + 1)) || !up(h->col_ptr, col_ptr, sizeof(int32_t) * (n + 1)) ||
-        !up(h->col_idx, col_idx, sizeof(int32_t) * nnz) || !up(h->row_idx, row_idx, sizeof(int32_t) * nnz) ||
-        (values && !up(h->val, values, sizeof(float) * nnz)))
-        return bail(fail(PE_EDEVICE, "upload failed"));
-    int32_t err = 0;
-    if (hipMemset(h->flags, 0, sizeof(int32_t)) != hipSuccess) return bail(fail(PE_EDEVICE, "hipMemset failed"));
-    k_csc2csr<<<blocks_for(n), 256>>>(n, h->row_ptr, h->col_idx, h->col_ptr, h->row_idx, h->csc2csr, h->flags);
-    k_edge_row<<<blocks_for(n), 256>>>(n, h->row_ptr, h->edge_row);
-    if (values) k_gather_f32<<<blocks_for(nnz), 256>>>(nnz, h->val, h->csc2csr, h->val_csc);
-    if (hipGetLastError() != hipSuccess || hipMemcpy(&err, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-        return bail(fail(PE_EDEVICE, "edge map kernel failed"));
-    if (err) return bail(fail(PE_EINVAL, "CSR and CSC hold different entries"));
+    if (count < 1 || !n || !nnz || !row_ptr || !col_idx || !col_ptr || !row_idx)
+        return fail(PE_EINVAL, "count must be >= 1 and the array-of-arrays arguments non-NULL");
+    // host-side validation first: no device work for malformed input
+    for (int32_t b = 0; b < count; ++b) {
+        if (n[b] <= 0) return fail(PE_EINVAL, "n must be positive");
+        if (nnz[b] < 0 || nnz[b] >= (int64_t)1 << 31) return fail(PE_EINVAL, "nnz out of range");
+        if (nnz[b] > 0 && (!col_idx[b] || !row_idx[b])) return fail(PE_EINVAL, "null index array");
+        int rc;
+        if ((rc = check_lists(n[b], nnz[b], row_ptr[b], col_idx[b], "CSR"))) return rc;
+        if ((rc = check_lists(n[b], nnz[b], col_ptr[b], row_idx[b], "CSC"))) return rc;
+        if (values && values[b])
+            for (int64_t p = 0; p < nnz[b]; ++p)
+                if (!(values[b][p] > 0.0f) || !std::isfinite(values[b][p]))
+                    return fail(PE_EINVAL, "values must be finite and > 0");
+        if (values && !values[b] && nnz[b] > 0) return fail(PE_EINVAL, "values[b] is NULL in a weighted batch");
+    }
+    perm_est *h = nullptr;
+    int rc = new_handle(opts, &h);
+    if (rc) { perm_est_destroy(h); return rc; }
+    h->mats.resize(count);
+    for (int32_t b = 0; b < count; ++b) {
+        rc = make_matrix(h, n[b], nnz[b], row_ptr[b], col_idx[b], col_ptr[b], row_idx[b],
+                         values ? values[b] : nullptr, h->mats[b]);
+        if (rc) { perm_est_destroy(h); return rc; }
+    }
     *out = h;
     return PE_OK;
 }
@@ -482,10 +838,9 @@ int perm_est_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_
 void perm_est_destroy(perm_est_t *h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
-    for (auto &P : h->preps) P.release();
-    dfree(h->row_ptr); dfree(h->col_idx); dfree(h->col_ptr); dfree(h->row_idx); dfree(h->csc2csr);
-    dfree(h->edge_row); dfree(h->val); dfree(h->val_csc);
-    dfree(h->hbm_state); dfree(h->work); dfree(h->work_totals); dfree(h->stats); dfree(h->seg); dfree(h->flags);
+    for (auto &M : h->mats) M.release();
+    dfree(h->hbm_state); dfree(h->work); dfree(h->work_totals); dfree(h->flags); dfree(h->batch_dev);
+    dfree(h->args_dev); dfree(h->order_dev); dfree(h->item_off_dev); dfree(h->seg_dev); dfree(h->stats);
     dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -497,158 +852,15 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count, uint64_t see
                        uint8_t *alive, uint64_t *path_hash, int32_t *path, int32_t *counters,
                        void *stream) {
     if (!h || !res) return fail(PE_EINVAL, "null handle or result");
+    if (h->mats.size() != 1) return fail(PE_EINVAL, "handle holds a batch: use perm_est_run_batch");
     if (count < 1 || first < 0 || first + count > ((int64_t)1 << 32))
         return fail(PE_EINVAL, "trajectory range must lie in [0, 2^32) and be non-empty");
     int rc;
     if ((rc = check_schedule(sched))) return rc;
     PE_HIP(hipSetDevice(h->device));
-    hipStream_t s = (hipStream_t)stream;
-    Prepared *P;
-    if ((rc = get_prepared(h, sched->initial_dm, sched->K0, s, &P))) return rc;
-    const int32_t n = h->n;
-
-    // ---- buffers for outputs the caller did not ask for
-    if (!logw || !alive || !counters) {
-        if (h->tmp_cap < count) {
-            dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
-            h->tmp_cap = 0;
-            if ((rc = dalloc(&h->tmp_logw, count)) || (rc = dalloc(&h->tmp_alive, count)) ||
-                (rc = dalloc(&h->tmp_counters, 4 * count)))
-                return rc;
-            h->tmp_cap = count;
-        }
-    }
-    double *lw = logw ? logw : h->tmp_logw;
-    uint8_t *al = alive ? alive : h->tmp_alive;
-    int32_t *cn = counters ? counters : h->tmp_counters;
-
-    // ---- per-trajectory state layout
-    const bool own_rc = sched->sk_policy != PE_SK_NONE;
-    const bool local = sched->sk_policy == PE_SK_LOCAL;
-    const bool dm = sched->dm_policy != PE_DM_NONE;
-    StateLayout L{};
-    uint64_t o = 0;
-    auto take = [&](uint64_t bytes) { uint32_t at = align_up(o, 16); o = (uint64_t)at + bytes; return at; };
-    L.deg = take((uint64_t)P->n_leaf * 2);
-    L.rec = take(own_rc ? 16ull * n : 0);
-    L.lst_a = take(4ull * P->dmax);
-    L.lst_b = take(4ull * P->dmax);
-    L.loc_r = take(local ? 4ull * n : 0);
-    L.loc_c = take(local ? 4ull * n : 0);
-    L.new_v = take(local ? 8ull * n : 0);
-    L.rem = take(dm ? 4ull * ((P->m + 31) / 32) : 0);
-    L.mate_r = take(dm ? 4ull * n : 0);
-    L.mate_c = take(dm ? 4ull * n : 0);
-    L.ws = take(dm ? 24ull * n : 0);
-    L.bytes = align_up(o, 256);
-    if (o >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
-
-    TrajArgs a{};
-    a.A = DevMat{n, (int32_t)P->m, P->row_ptr, P->col_idx, P->col_ptr, P->row_idx, P->csc2csr,
-                 P->edge_row, P->val, P->val_csc};
-    a.r0 = P->r0;
-    a.c0 = P->c0;
-    a.deg0 = P->deg0;
-    a.tree0 = P->tree0;
-    a.mate0_r = P->mate_r;
-    a.mate0_c = P->mate_c;
-    a.n_leaf = P->n_leaf;
-    a.tree = P->tree;
-    a.st = L;
-    a.ok0 = P->ok;
-    a.vertex_rule = sched->vertex_rule;
-    a.sk_policy = sched->sk_policy;
-    a.dm_policy = sched->dm_policy;
-    a.K = sched->K;
-    a.scaled = (P->r0 != nullptr) || own_rc;
-    a.theta_th = sched->theta_th;
-    a.theta_tr = sched->theta_tr;
-    a.seed = seed;
-    a.b = 0;
-    a.first = first;
-    a.count = count;
-    a.logw = lw;
-    a.alive = al;
-    a.path_hash = path_hash;
-    a.path = path;
-    a.counters = cn;
-    a.work_next = h->work;
-    a.err = h->work + 1;
-    a.work_totals = h->work_totals;
-
-    // ---- tier and launch shape
-    const size_t tree_bytes = (size_t)P->tree.total * 4;
-    const size_t lds_wave = tree_bytes + L.bytes;
-    const size_t kLdsBlock = 64 * 1024, kLdsCU = 160 * 1024;
-    int wpb;
-    unsigned blocks;
-    size_t shmem;
-    if (lds_wave <= 32 * 1024 && !(h->opt_flags & PE_FLAG_FORCE_HBM)) {
-        a.hbm_state = nullptr;
-        a.lds_state_bytes = (int32_t)L.bytes;
-        wpb = (int)std::max<size_t>(1, std::min<size_t>(4, kLdsBlock / lds_wave));
-        shmem = (size_t)wpb * lds_wave;
-        const size_t per_cu = std::max<size_t>(1, std::min<size_t>(16 / wpb, kLdsCU / shmem));
-        blocks = (unsigned)std::min<int64_t>((count + wpb - 1) / wpb, (int64_t)h->cu_count * per_cu);
-    } else {
-        wpb = 4;
-        a.lds_state_bytes = 0;
-        shmem = (size_t)wpb * tree_bytes;
-        const size_t per_cu = std::max<size_t>(1, std::min<size_t>(4, kLdsCU / std::max<size_t>(shmem, 1)));
-        blocks = (unsigned)std::min<int64_t>((count + wpb - 1) / wpb, (int64_t)h->cu_count * per_cu);
-        const size_t need = (size_t)blocks * wpb * L.bytes;
-        if (h->hbm_bytes < need) {
-            dfree(h->hbm_state);
-            h->hbm_bytes = 0;
-            if ((rc = dalloc(&h->hbm_state, need))) return rc;
-            h->hbm_bytes = need;
-        }
-        a.hbm_state = h->hbm_state;
-        a.hbm_stride = L.bytes;
-    }
-    a.waves_per_block = wpb;
-
-    int64_t seg_host[2] = {0, count};
-    PE_HIP(hipMemcpyAsync(h->seg, seg_host, sizeof(seg_host), hipMemcpyHostToDevice, s));
-    k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
-    k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
-    k_fill_i32<<<1, 64, 0, s>>>(10, reinterpret_cast<int32_t *>(h->work_totals), 0);
-    PE_HIP(hipEventRecord(h->ev0, s));
-    launch_traj(sched->sk_policy, dm, P->val != nullptr, blocks, wpb * kWave, shmem, s, a);
-    PE_HIP(hipGetLastError());
-    k_reduce_stats<<<1, 1024, 0, s>>>(lw, al, cn, h->seg, h->stats);
-    PE_HIP(hipGetLastError());
-    PE_HIP(hipEventRecord(h->ev1, s));
-    DevStats st;
-    uint32_t err_bits = 0;
-    unsigned long long wt[5];
-    PE_HIP(hipMemcpyAsync(&st, h->stats, sizeof(st), hipMemcpyDeviceToHost, s));
-    PE_HIP(hipMemcpyAsync(wt, h->work_totals, sizeof(wt), hipMemcpyDeviceToHost, s));
-    PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
-    PE_HIP(hipStreamSynchronize(s));
-    if (err_bits) return fail(PE_EDEVICE, "trajectory kernel reported an internal inconsistency (bits " +
-                                              std::to_string(err_bits) + ")");
-    float ms = 0.0f;
-    PE_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    res->log_estimate = st.log_estimate;
-    res->p_match = st.p_match;
-    res->rel_spread = st.rel_spread;
-    res->rse = st.rse;
-    res->ess = st.ess;
-    res->var_logw = st.var_logw;
-    res->max_logw = st.max_logw;
-    res->n_traj = st.n_traj;
-    res->n_alive = st.n_alive;
-    res->n_dm = st.n_dm;
-    res->n_full_sk = st.n_full_sk;
-    res->n_local_sk = st.n_local_sk;
-    res->n_steps = st.n_steps;
-    res->seconds = ms * 1e-3;
-    res->n_entries_scanned = (int64_t)wt[0];
-    res->n_decrements = (int64_t)wt[1];
-    res->n_local_entries = (int64_t)wt[2];
-    res->n_local_values = (int64_t)wt[3];
-    return PE_OK;
+    std::vector<RunPart> parts(1);
+    parts[0] = RunPart{first, count, logw, alive, path_hash, path, counters};
+    return launch(h, sched, seed, parts, res, (hipStream_t)stream, 0, 0, nullptr);
 }
 
 int perm_est_run(perm_est_t *h, int64_t n_traj, uint64_t seed, const perm_est_schedule *sched,
@@ -656,6 +868,33 @@ int perm_est_run(perm_est_t *h, int64_t n_traj, uint64_t seed, const perm_est_sc
                  void *stream) {
     return perm_est_run_range(h, 0, n_traj, seed, sched, res, logw, alive, path_hash, nullptr, nullptr,
                               stream);
+}
+
+int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed, const perm_est_schedule *sched,
+                       perm_est_result *res, double *logw, uint8_t *alive, uint64_t *path_hash,
+                       int32_t flags, void *stream) {
+    if (!h || !res || !n_traj) return fail(PE_EINVAL, "null handle, result or n_traj");
+    if (flags & ~PE_RUN_AUTOTUNE) return fail(PE_EINVAL, "unknown run flags");
+    int rc;
+    if ((rc = check_schedule(sched))) return rc;
+    PE_HIP(hipSetDevice(h->device));
+    const size_t count = h->mats.size();
+    std::vector<RunPart> parts(count);
+    int64_t off = 0;
+    for (size_t b = 0; b < count; ++b) {
+        if (n_traj[b] < 1 || n_traj[b] >= ((int64_t)1 << 32))
+            return fail(PE_EINVAL, "every matrix needs 1 <= n_traj < 2^32");
+        parts[b].count = n_traj[b];
+        parts[b].logw = logw ? logw + off : nullptr;
+        parts[b].alive = alive ? alive + off : nullptr;
+        parts[b].path_hash = path_hash ? path_hash + off : nullptr;
+        off += n_traj[b];
+    }
+    int wpb = 0, per_cu = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PE_RUN_AUTOTUNE)
+        if ((rc = tuned_shape(h, sched, seed, parts, s, &wpb, &per_cu))) return rc;
+    return launch(h, sched, seed, parts, res, s, wpb, per_cu, nullptr);
 }
 
 }  // extern "C"

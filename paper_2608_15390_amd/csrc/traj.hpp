@@ -77,15 +77,7 @@ struct TrajArgs {
     uint64_t *path_hash;
     int32_t *path;             // [count][2n] or nullptr
     int32_t *counters;         // [count][4] or nullptr
-    uint32_t *work_next;       // work counter (zeroed before launch)
     uint32_t *err;             // internal-consistency error bits (zeroed before launch)
-    unsigned long long *work_totals;  // [5] adjacency entries scanned at the two
-                                      // endpoints, degree decrements, local-repair
-                                      // entries, local values, full SK sweeps
-    char *hbm_state;           // HBM tier: base of per-wave slots; nullptr = LDS tier
-    uint64_t hbm_stride;
-    int32_t lds_state_bytes;   // LDS tier: bytes of state per wave
-    int32_t waves_per_block;
 };
 
 // ------------------------------------------------------------------ views
@@ -438,6 +430,17 @@ struct Traj {
 };
 
 // ------------------------------------------------------------ helpers
+// per-wave work units (kept in registers, added once to the launch totals:
+// adjacency entries scanned at the two endpoints, degree decrements,
+// local-repair entries, local values, full SK sweeps)
+struct Work {
+    uint64_t scan = 0;        // adjacency entries read at the two endpoints
+    uint64_t dec = 0;         // residual-degree decrements
+    uint64_t loc_entries = 0; // entries gathered or summed by local repairs
+    uint64_t loc_values = 0;  // scaling values recomputed by local repairs
+    uint64_t sweeps = 0;      // full SK iterations
+};
+
 __device__ __forceinline__ uint64_t lemire_from(uint64_t x, uint64_t W, uint64_t seed, uint32_t k,
                                                 uint32_t b, uint32_t t) {
     const uint64_t lo = x * W;
@@ -477,8 +480,8 @@ __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total)
 // is marked with stamps (step+1) << 6 | lane; when several lanes reach the
 // same vertex in one instruction the lane whose stamp survives keeps it.
 template <class TT>
-__device__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
-                                   uint64_t *work) {
+__device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
+                                                   Work &work) {
     const TrajArgs &a = T.a;
     const int l = lane_id();
     const int32_t n = T.n;
@@ -570,8 +573,8 @@ __device__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, in
         }
     }
     wave_fence();
-    work[2] += (uint64_t)(TG + TR) + wave_sum_u64(summed);
-    work[3] += (uint64_t)ne;
+    work.loc_entries += (uint64_t)(TG + TR) + wave_sum_u64(summed);
+    work.loc_values += (uint64_t)ne;
 }
 
 // Eq. (local) with lists kept in memory (either list longer than a wave):
@@ -579,7 +582,7 @@ __device__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, in
 template <class TT>
 __device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t k_rho, int32_t skip_rho,
                                    const int32_t *gam_list, int32_t k_gam, int32_t skip_gam, int32_t t,
-                                   uint64_t *work) {
+                                   Work &work) {
     const int l = lane_id();
     const int32_t n = T.n;
     const int32_t mark = t + 1;
@@ -653,14 +656,14 @@ __device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t
         T.rec[x].s = T.new_v[idx];
     }
     wave_fence();
-    work[2] += gathered + wave_sum_u64(summed);
-    work[3] += (uint64_t)ne;
+    work.loc_entries += gathered + wave_sum_u64(summed);
+    work.loc_values += (uint64_t)ne;
 }
 
 // ------------------------------------------------------------------ kernel
 template <int SK, bool DM, bool WT>
-__device__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, WT> &T, int64_t q,
-                               uint64_t *work) {
+__device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, WT> &T,
+                                               int64_t q, Work &work) {
     constexpr bool OWN = SK != kSkNone;
     const int l = lane_id();
     const int32_t n = a.A.n;
@@ -921,8 +924,8 @@ __device__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, 
                 if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
             }
         }
-        work[0] += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
-        work[1] += (uint64_t)(kc - 1 + kb);
+        work.scan += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
+        work.dec += (uint64_t)(kc - 1 + kb);
         wave_fence();
         // refresh the group of v from the leaves read at selection time
         if (gsel >= 0) {
@@ -977,7 +980,7 @@ __device__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, 
             }
             for (int it = 0; it < nit; ++it) T.sk_sweep();
             n_sweeps += nit;
-            work[4] += (uint64_t)nit;
+            work.sweeps += (uint64_t)nit;
         } else if (SK == kSkLocal) {
             // rho_list = N_t(rho)\{gam} (columns), gam_list = N_t(gam)\{rho} (rows)
             if (fast_v && fast_u) {
@@ -1015,36 +1018,65 @@ __device__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, 
     wave_fence();
 }
 
+// A launch runs the trajectories of one or more matrices (same schedule).
+// Work items are numbered over the matrices taken in `order` (most
+// expensive first, for a short tail); item q maps to matrix order[i] with
+// item_off[i] <= q < item_off[i+1] and trajectory q - item_off[i].
+struct BatchArgs {
+    const TrajArgs *mats;     // [count] per-matrix argument blocks (device)
+    const int32_t *order;     // [count] processing order
+    const int64_t *item_off;  // [count+1] prefix sums of trajectory counts, in order
+    int32_t count;
+    int64_t total;
+    uint32_t *work_next;      // item counter (zeroed before launch)
+    unsigned long long *work_totals;  // [5], see TrajArgs
+    char *hbm_state;          // HBM tier: base of per-wave slots; nullptr = LDS tier
+    uint64_t hbm_stride;
+    int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
+    int32_t lds_state_bytes;  // LDS tier: bytes of state per wave
+    int32_t waves_per_block;
+};
+
+// The argument blocks live in device memory (uniform fields become scalar
+// loads; no private copy of a by-value parameter is needed).
 template <int SK, bool DM, bool WT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SK == kSkNone ? 4 : 1, 8)))
-traj_kernel(TrajArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || !DM) ? 4 : 1, 8)))
+traj_kernel(const BatchArgs *__restrict__ bp) {
+    const BatchArgs &B = *bp;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x / kWave;
-    const size_t per_wave = (size_t)a.tree.total * 4 + (size_t)a.lds_state_bytes;
+    const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_state_bytes;
     char *mine = smem + (size_t)wave * per_wave;
     uint32_t *tree = reinterpret_cast<uint32_t *>(mine);
     char *state;
-    if (a.hbm_state) {
-        const uint64_t slot = (uint64_t)blockIdx.x * a.waves_per_block + wave;
-        state = a.hbm_state + slot * a.hbm_stride;
+    if (B.hbm_state) {
+        const uint64_t slot = (uint64_t)blockIdx.x * B.waves_per_block + wave;
+        state = B.hbm_state + slot * B.hbm_stride;
     } else {
-        state = mine + (size_t)a.tree.total * 4;
+        state = mine + B.lds_tree_bytes;
     }
-    const Traj<SK != kSkNone, DM, WT> T(a, state, tree);
-    uint64_t work[5] = {0, 0, 0, 0, 0};
+    Work work;
     for (;;) {
         uint32_t q = 0;
-        if (lane_id() == 0) q = atomicAdd(a.work_next, 1u);
+        if (lane_id() == 0) q = atomicAdd(B.work_next, 1u);
         q = read_lane(q, 0);
-        if ((int64_t)q >= a.count) break;
-        run_trajectory<SK, DM, WT>(a, T, (int64_t)q, work);
+        if ((int64_t)q >= B.total) break;
+        // matrix of item q: last i with item_off[i] <= q
+        int32_t lo = 0, hi = B.count - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (B.item_off[mid] <= (int64_t)q) lo = mid; else hi = mid - 1;
+        }
+        const TrajArgs &a = B.mats[B.order[lo]];
+        const Traj<SK != kSkNone, DM, WT> T(a, state, tree);
+        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work);
     }
-    if (lane_id() == 0 && a.work_totals) {
-        atomicAdd(a.work_totals + 0, (unsigned long long)work[0]);
-        atomicAdd(a.work_totals + 1, (unsigned long long)work[1]);
-        atomicAdd(a.work_totals + 2, (unsigned long long)work[2]);
-        atomicAdd(a.work_totals + 3, (unsigned long long)work[3]);
-        atomicAdd(a.work_totals + 4, (unsigned long long)work[4]);
+    if (lane_id() == 0 && B.work_totals) {
+        atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);
+        atomicAdd(B.work_totals + 1, (unsigned long long)work.dec);
+        atomicAdd(B.work_totals + 2, (unsigned long long)work.loc_entries);
+        atomicAdd(B.work_totals + 3, (unsigned long long)work.loc_values);
+        atomicAdd(B.work_totals + 4, (unsigned long long)work.sweeps);
     }
 }
 

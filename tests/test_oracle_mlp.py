@@ -1,0 +1,142 @@
+"""Pins of the FP64 network reference and of the learned proposal."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as R
+from oracle import oracle as O
+from paper_2608_15390_amd import inputs as G
+from oracle_tools import dense_values, enumerate_tree
+
+
+def _data(seed, groups=12):
+    g = np.random.default_rng(seed)
+    sizes = g.integers(2, 7, size=groups)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    X = g.normal(0, 1, (off[-1], R.IN))
+    X[:, 6:] = 0
+    y = np.empty(off[-1])
+    for a, b in zip(off[:-1], off[1:]):
+        p = g.random(b - a) + 0.05
+        y[a:b] = p / p.sum()
+    return X, y, off
+
+
+def test_backward_matches_finite_differences():
+    X, y, off = _data(1)
+    th = R.init(3)
+    _, grad = R.loss_and_grad(th, X, y, off)
+    g = np.random.default_rng(5)
+    for idx in g.choice(R.NPARAM, 60, replace=False):
+        e = np.zeros(R.NPARAM)
+        e[idx] = 1e-6
+        lp, _ = R.loss_and_grad(th + e, X, y, off)
+        lm, _ = R.loss_and_grad(th - e, X, y, off)
+        fd = (lp - lm) / 2e-6
+        assert grad[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_gradient_vanishes_when_the_network_already_matches_the_targets():
+    X, _, off = _data(2)
+    th = R.init(4)
+    L, _ = R.forward(th, X)
+    y = R.softmax_groups(L, off)
+    loss, grad = R.loss_and_grad(th, X, y, off)
+    assert np.abs(grad).max() < 1e-12
+    # and the loss equals the mean entropy of the targets
+    ent = -sum(np.sum(y[a:b] * np.log(y[a:b])) for a, b in zip(off[:-1], off[1:])) / (len(off) - 1)
+    assert loss == pytest.approx(ent, rel=1e-12)
+
+
+def test_plog2_is_piecewise_linear_log2():
+    for k in range(-20, 21):
+        assert O.plog2(2.0 ** k) == k
+    assert O.plog2(3.0) == 1.5
+    assert O.plog2(0.75) == -0.5
+    xs = np.geomspace(1e-6, 1e6, 200)
+    v = [O.plog2(x) for x in xs]
+    assert all(b >= a for a, b in zip(v, v[1:]))
+    assert max(abs(p - math.log2(x)) for p, x in zip(v, xs)) < 0.09
+
+
+def _float32_logit(model, x, order8, order64):
+    """The grid network in float32 with permuted summation orders."""
+    W1, b1, W2, b2, w3, b3 = [np.asarray(a, dtype=np.float32) for a in R.unpack(model)]
+    x = np.asarray(x, dtype=np.float32)
+    q = lambda a: np.float32(min(max(np.rint(max(float(a), 0.0) * 64), 0), 255) / 64)  # noqa: E731
+    h1 = np.array([q(_sum32(b1[j], [x[k] * W1[k, j] for k in order8])) for j in range(64)], np.float32)
+    h2 = np.array([q(_sum32(b2[j], [h1[k] * W2[k, j] for k in order64])) for j in range(64)], np.float32)
+    acc = _sum32(b3[0], [h2[k] * w3[k] for k in order64])
+    return int(min(max(np.rint(float(acc) * 16), -1024), 1023))
+
+
+def _sum32(start, terms):
+    acc = np.float32(start)
+    for t in terms:
+        acc = np.float32(acc + np.float32(t))
+    return acc
+
+
+def test_grid_network_is_exact_in_float32_in_any_order():
+    """Every partial sum of the quantised network is a float32 number, so a
+    float32 evaluation in any summation order reproduces the oracle."""
+    g = np.random.default_rng(7)
+    model = R.quantize(R.init(9, scale=1.5))
+    for trial in range(8):
+        x = O.learned_features(int(g.integers(0, 40)), int(g.integers(0, 40)), float(g.uniform(0.01, 3)),
+                               float(g.uniform(0.01, 3)), int(g.integers(0, 100)), 100, trial % 2)
+        ref = O.learned_logit(model, x)
+        for _ in range(3):
+            order8 = [int(i) for i in g.permutation(8)]
+            order64 = [int(i) for i in g.permutation(64)]
+            assert _float32_logit(model, x, order8, order64) == ref
+
+
+def test_learned_weights_properties():
+    for k in (2, 3, 7, 30):
+        g = np.random.default_rng(k)
+        L = g.integers(-300, 300, size=k)
+        w = O.learned_weights(L, 0.05).astype(np.int64)
+        assert (w >= 1).all()
+        assert abs(int(w.sum()) - 2 ** 24) <= k
+        assert (w >= int(0.05 * 2 ** 24 / k) - 1).all()      # the uniform share
+        order = np.argsort(-L, kind="stable")
+        assert (np.diff(w[order]) <= 0).all()                  # monotone in the logit
+    # equal logits give equal weights
+    w = O.learned_weights([5, 5, 5, 5], 0.3)
+    assert len(set(w.tolist())) == 1
+
+
+def _learned(model, **kw):
+    base = O.preset("local_nodm")
+    return base.replace(sk_policy=O.SK_LEARNED, model=model, **kw)
+
+
+@pytest.mark.parametrize("initial_dm", [0, 1])
+def test_learned_proposal_enumeration_is_exact(initial_dm):
+    """Unbiasedness with the learned proposal: the weight uses the
+    probability actually sampled, so E[X] = per(A) exactly."""
+    model = R.quantize(R.init(11, scale=2.0))
+    sched = _learned(model, initial_dm=initial_dm, K0=20 if initial_dm else 0)
+    g = np.random.default_rng(12)
+    for t in range(10):
+        n = int(g.integers(2, 8))
+        M = G.planted_bernoulli(n, float(g.uniform(0.2, 0.7)), int(g.integers(1 << 30)), planted="random")
+        if t % 3 == 0:
+            M = G.with_weights(M, t)
+        A = O.OMatrix(M)
+        pre = O.prep(A, sched)
+        E, _, _ = enumerate_tree(A, sched, pre)
+        assert E == pytest.approx(O.ryser_f64(dense_values(M)), rel=1e-12)
+
+
+def test_learned_proposal_mean_within_ci():
+    model = R.quantize(R.init(13))
+    M = G.config_small(2)
+    per = O.ryser(G.to_dense(M))
+    out = O.run(O.OMatrix(M), _learned(model), seed=3, count=20000, nthreads=8)
+    st = O.stats(out["logw"], out["alive"])
+    assert abs(math.exp(st["log_estimate"]) / per - 1) <= 4.5 * st["rse"]

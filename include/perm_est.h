@@ -60,6 +60,9 @@ extern "C" {
 #define PE_SK_FIXED 1     /* K full SK iterations on every child            */
 #define PE_SK_ADAPTIVE 2  /* ceil((1 - z) K) full iterations, clamped [0,K] */
 #define PE_SK_LOCAL 3     /* one local Jacobi repair per step, Eq. (local)  */
+#define PE_SK_LEARNED 4   /* learned per-edge proposal in place of the
+                             scaling scores of Eq. (q); no inner SK.  Needs
+                             perm_est_set_model on the handle first         */
 
 /* support-filtering policy P_DM (Sec. 3.3) */
 #define PE_DM_NONE 0
@@ -137,7 +140,9 @@ int perm_est_create(int32_t n, int64_t nnz,
  * "fixed_all", "adaptive_threshold", "local_threshold", "adaptive_tracked",
  * "local_tracked" (two-sided MD, K0 = 100, K = 10, theta = 0.33, shared
  * initial DM) -- and "plain" (Alg. 2 with MD, no scaling, no filtering),
- * "rasmussen" (Alg. 1), "local_nodm" (local_threshold without inner DM).
+ * "rasmussen" (Alg. 1), "local_nodm" (local_threshold without inner DM),
+ * "learned" and "learned_threshold" (PE_SK_LEARNED with no inner DM / with
+ * Thrs, otherwise as the five variants; the network is set separately).
  * Errors: PE_EINVAL for an unknown name. */
 int perm_est_schedule_preset(const char *name, perm_est_schedule *out);
 
@@ -199,6 +204,110 @@ int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed,
                        const perm_est_schedule *sched, perm_est_result *res,
                        double *logw, uint8_t *alive, uint64_t *path_hash,
                        int32_t flags, void *stream);
+
+/* ------------------------------------------------------------------
+ * Learned proposal.  A per-edge network scores every candidate u of the
+ * selected vertex v; its softmax, mixed with the uniform distribution,
+ * replaces the proposal of Eq. (q).  The importance weight of Alg. 2 still
+ * divides by the probability actually sampled, so every estimate stays
+ * unbiased (Sec. 2, Eq. (per1)) whatever the network computes.
+ *
+ * Network: 8 features -> 64 ReLU -> 64 ReLU -> 1 logit; PE_MLP_NPARAM
+ * float parameters packed as W1[8][64], b1[64], W2[64][64], b2[64], w3[64],
+ * b3 (row-major, input index first).  Features of the candidate edge
+ * (rho = its row end, gam = its column end) at step t:
+ *   x0 = min(deg rho, 255)/64, x1 = min(deg gam, 255)/64 (residual degrees),
+ *   x2 = Q(plog2(r0[rho])/4), x3 = Q(plog2(c0[gam])/4) (outer scaling
+ *   after the K0 shared SK iterations, 1 if K0 = 0), x4 = Q(t/n),
+ *   x5 = 1 if v is a row, x6 = x7 = 0;
+ *   Q(y) = clamp(rint(64 y), -256, 255)/64 and plog2(m 2^e) = e - 2 + 2m for
+ *   m in [0.5, 1).
+ * Sampling uses the network on an exact grid (results are bit-reproducible
+ * against a scalar evaluation): parameters snapped to multiples of 1/64 in
+ * [-127/64, 127/64], hidden activations to multiples of 1/64 in
+ * [0, 255/64], the logit to L = clamp(rint(16 y), -1024, 1023); then
+ * E_i = rint(2^24 exp(-(L_max - L_i)/16)) (0 once the gap reaches 2048) and
+ * integer weights w_i = max(1, rint(2^24 ((1 - alpha) E_i / sum E + alpha/k)))
+ * over the k candidates.  z of the Thrs / Trck policies is w_u / sum w.
+ * ------------------------------------------------------------------ */
+#define PE_MLP_NPARAM 4801
+
+/* Install the learned proposal's network on handle h.
+ *   params:    device float[PE_MLP_NPARAM] (caller-owned, read once; the
+ *              handle keeps its own snapped copy).
+ *   mix_alpha: uniform share alpha in [0, 1].
+ * Errors: PE_EINVAL (NULL params, alpha outside [0, 1], a non-finite
+ * parameter), PE_ENOMEM, PE_EDEVICE. */
+int perm_est_set_model(perm_est_t *h, const float *params, double mix_alpha, void *stream);
+
+/* Training-pair buffers (all DEVICE memory, caller-owned).  A group is one
+ * recorded step: the candidates of the selected vertex in adjacency order. */
+typedef struct {
+    float *x;          /* float[rec_cap][8] features (16-byte aligned)       */
+    float *y;          /* float[rec_cap] proposal of the running schedule,
+                          normalised over the group (the training target)   */
+    int64_t *gstart;   /* int64[group_cap] first record of each group        */
+    int32_t *ginfo;    /* int32[group_cap][4] = {k, matrix b, trajectory id
+                          (bits of a uint32), step t}                       */
+    int64_t rec_cap;   /* in [2, 2^31)                                      */
+    int64_t group_cap; /* in [1, 2^31)                                      */
+    int32_t stride;    /* record steps t with t % stride == 0 (>= 1)        */
+    int32_t reserved;  /* must be 0                                         */
+} perm_est_record_buffers;
+
+/* Run the batch as perm_est_run_batch (same trajectories, same results in
+ * res) and record training pairs from it: at every recorded step with at
+ * least two candidates and a vertex list of at most 64 entries, the
+ * features above and the schedule's own proposal of Eq. (q) (with
+ * PE_SK_FIXED, K full SK iterations on the residual) for each candidate.
+ * Groups that do not fit are dropped; the written groups are a prefix of
+ * one claim order, with contiguous records, but that order is not
+ * deterministic (compare sets keyed by ginfo).
+ *   n_records, n_groups: host; how many were written.
+ * Errors: as perm_est_run_batch; PE_EINVAL for PE_SK_LEARNED or bad
+ * buffers. */
+int perm_est_record(perm_est_t *h, const int64_t *n_traj, uint64_t seed,
+                    const perm_est_schedule *sched, const perm_est_record_buffers *buf,
+                    perm_est_result *res, int64_t *n_records, int64_t *n_groups,
+                    void *stream);
+
+/* Trainer of the network (float master parameters and Adam moments on one
+ * device).  Training minimises the listwise softmax cross-entropy over
+ * groups, loss = (1/G) sum_g -sum_{i in g} y_i ln softmax(L_g)_i, so
+ * d loss / d L_i = (softmax_i - y_i) / G; the two hidden layers run on
+ * bf16 matrix cores with float accumulation. */
+typedef struct perm_est_mlp perm_est_mlp_t;
+
+/* params: host float[PE_MLP_NPARAM] initial values.
+ * Errors: PE_EINVAL, PE_ENOMEM, PE_EDEVICE. */
+int perm_est_mlp_create(int32_t device, const float *params, perm_est_mlp_t **out);
+
+/* Copy the trainer's current float[PE_MLP_NPARAM] parameters to `out`
+ * (host or device memory).  Errors: PE_EINVAL (NULL), PE_EDEVICE. */
+int perm_est_mlp_get_params(perm_est_mlp_t *t, float *out, void *stream);
+
+/* logits[i] of the float network (no grid) for device x[n][8]; device
+ * logits[n].  Errors: PE_EINVAL (n < 0, NULL), PE_EDEVICE. */
+int perm_est_mlp_forward(perm_est_mlp_t *t, const float *x, int64_t n, float *logits, void *stream);
+
+/* Loss over groups g0..g1-1 of a recording (gstart/ginfo as written by
+ * perm_est_record: groups contiguous in records) into *loss (host) and its
+ * gradient into device grad[PE_MLP_NPARAM] (overwritten; may be NULL).
+ * Errors: PE_EINVAL (empty or negative window), PE_ENOMEM, PE_EDEVICE. */
+int perm_est_mlp_loss_grad(perm_est_mlp_t *t, const float *x, const float *y, const int64_t *gstart,
+                           const int32_t *ginfo, int64_t g0, int64_t g1, double *loss, float *grad,
+                           void *stream);
+
+/* Train for `epochs` passes over groups 0..n_groups-1 in windows of
+ * `batch_groups` consecutive groups, window order reshuffled each epoch
+ * from `seed`; Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ * after every window.  loss_per_epoch: host double[epochs] (mean window
+ * loss), or NULL.  Errors: PE_EINVAL, PE_ENOMEM, PE_EDEVICE. */
+int perm_est_mlp_train(perm_est_mlp_t *t, const float *x, const float *y, const int64_t *gstart,
+                       const int32_t *ginfo, int64_t n_groups, int32_t epochs, int64_t batch_groups,
+                       double lr, uint64_t seed, double *loss_per_epoch, void *stream);
+
+void perm_est_mlp_destroy(perm_est_mlp_t *t);
 
 /* Release every device and host resource of the handle (NULL is a no-op). */
 void perm_est_destroy(perm_est_t *h);

@@ -158,6 +158,9 @@ def preset(name: str) -> Schedule:
         "local_tracked": Schedule(sk_policy=SK_LOCAL, dm_policy=DM_TRCK, **both),
         # local repair every step, no inner filtering (large-n workload)
         "local_nodm": Schedule(sk_policy=SK_LOCAL, dm_policy=DM_NONE, **both),
+        # learned proposal (the network goes in Schedule.model)
+        "learned": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_NONE, **both),
+        "learned_threshold": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_THRS, **both),
     }
     if name not in table:
         raise KeyError(name)

@@ -19,13 +19,14 @@ import numpy as np
 from . import _native as N
 from .inputs import SparseMatrix
 
-__all__ = ["PermEst", "PermEstBatch", "preset", "Schedule", "PermEstError"]
+__all__ = ["PermEst", "PermEstBatch", "ProposalNet", "preset", "Schedule", "PermEstError"]
 
 PermEstError = N.PermEstError
 Schedule = N.Schedule
 
 VR_MD, VR_ROW_ORDER = 0, 1
-SK_NONE, SK_FIXED, SK_ADAPTIVE, SK_LOCAL = 0, 1, 2, 3
+SK_NONE, SK_FIXED, SK_ADAPTIVE, SK_LOCAL, SK_LEARNED = 0, 1, 2, 3, 4
+MLP_NPARAM = N.PE_MLP_NPARAM
 DM_NONE, DM_ALL, DM_THRS, DM_TRCK = 0, 1, 2, 3
 
 
@@ -43,7 +44,21 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else int(t.data_ptr())
 
 
-class PermEst:
+class _ModelMixin:
+    def set_model(self, params, mix_alpha: float = 0.05, stream=None):
+        """Install the learned proposal's network: params is a float32
+        device tensor of MLP_NPARAM values (snapped to the inference grid by
+        the library)."""
+        import torch
+
+        if params.dtype != torch.float32 or not params.is_cuda or params.numel() != MLP_NPARAM:
+            raise ValueError("params must be a float32 device tensor of MLP_NPARAM values")
+        params = params.contiguous()
+        st = stream if stream is not None else torch.cuda.current_stream(params.device)
+        N.check(self._lib.perm_est_set_model(self._h, _ptr(params), float(mix_alpha), C.c_void_p(st.cuda_stream)))
+
+
+class PermEst(_ModelMixin):
     """One sparse matrix resident on one GPU."""
 
     def __init__(self, M: SparseMatrix, device: int = 0, force_hbm: bool = False):
@@ -101,7 +116,7 @@ class PermEst:
         return out
 
 
-class PermEstBatch:
+class PermEstBatch(_ModelMixin):
     """Many matrices of uneven order resident on one GPU; every run executes
     all their trajectories in one persistent launch."""
 
@@ -171,3 +186,94 @@ class PermEstBatch:
             if v is not None:
                 out[k] = v
         return out
+
+    def record(self, n_traj, seed: int, schedule: N.Schedule, *, rec_cap: int, group_cap: int,
+               stride: int = 1, stream=None) -> Dict:
+        """Run the batch and record training pairs (features, proposal of the
+        running schedule) at every stride-th step; returns the statistics and
+        the written prefix of the recording as device tensors."""
+        import torch
+
+        counts = np.array([n_traj] * self.count if np.isscalar(n_traj) else list(n_traj), dtype=np.int64)
+        dev = torch.device("cuda", self.device)
+        x = torch.empty((rec_cap, 8), dtype=torch.float32, device=dev)
+        y = torch.empty(rec_cap, dtype=torch.float32, device=dev)
+        gs = torch.empty(group_cap, dtype=torch.int64, device=dev)
+        gi = torch.empty((group_cap, 4), dtype=torch.int32, device=dev)
+        buf = N.RecordBuffers(_ptr(x), _ptr(y), _ptr(gs), _ptr(gi), rec_cap, group_cap, stride, 0)
+        res = (N.Result * self.count)()
+        nr, ng = C.c_int64(), C.c_int64()
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        N.check(self._lib.perm_est_record(self._h, counts.ctypes.data, C.c_uint64(seed), C.byref(schedule),
+                                          C.byref(buf), res, C.byref(nr), C.byref(ng),
+                                          C.c_void_p(st.cuda_stream)))
+        nr, ng = nr.value, ng.value
+        return {"results": [r.as_dict() for r in res], "x": x[:nr], "y": y[:nr], "gstart": gs[:ng],
+                "ginfo": gi[:ng], "n_records": nr, "n_groups": ng}
+
+
+class ProposalNet:
+    """Trainer of the learned proposal's network on one GPU (float master
+    parameters, Adam moments), driving the library's matrix-core kernels."""
+
+    def __init__(self, params, device: int = 0):
+        import torch  # noqa: F401
+
+        self._lib = N.load()
+        self.device = device
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        self._h = C.c_void_p()
+        N.check(self._lib.perm_est_mlp_create(device, p.ctypes.data, C.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            self._lib.perm_est_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self, stream=None):
+        """A float32 device tensor copy of the current parameters."""
+        import torch
+
+        out = torch.empty(MLP_NPARAM, dtype=torch.float32, device=torch.device("cuda", self.device))
+        N.check(self._lib.perm_est_mlp_get_params(self._h, _ptr(out), self._stream(stream)))
+        return out
+
+    def _stream(self, stream):
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", self.device))
+        return C.c_void_p(st.cuda_stream)
+
+    def forward(self, x, stream=None):
+        import torch
+
+        x = x.contiguous()
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        N.check(self._lib.perm_est_mlp_forward(self._h, _ptr(x), x.shape[0], _ptr(out), self._stream(stream)))
+        return out
+
+    def loss_grad(self, rec: Dict, g0: int = 0, g1: Optional[int] = None, stream=None):
+        import torch
+
+        g1 = rec["n_groups"] if g1 is None else g1
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=rec["x"].device)
+        loss = C.c_double()
+        N.check(self._lib.perm_est_mlp_loss_grad(
+            self._h, _ptr(rec["x"]), _ptr(rec["y"]), _ptr(rec["gstart"]), _ptr(rec["ginfo"]), g0, g1,
+            C.byref(loss), _ptr(grad), self._stream(stream)))
+        return loss.value, grad
+
+    def train(self, rec: Dict, epochs: int, batch_groups: int, lr: float, seed: int = 0, stream=None):
+        losses = (C.c_double * max(epochs, 1))()
+        N.check(self._lib.perm_est_mlp_train(
+            self._h, _ptr(rec["x"]), _ptr(rec["y"]), _ptr(rec["gstart"]), _ptr(rec["ginfo"]),
+            rec["n_groups"], epochs, batch_groups, float(lr), C.c_uint64(seed), losses, self._stream(stream)))
+        return [losses[i] for i in range(epochs)]

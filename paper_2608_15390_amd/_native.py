@@ -61,6 +61,19 @@ class Result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class RecordBuffers(C.Structure):
+    _fields_ = [
+        ("x", C.c_void_p),
+        ("y", C.c_void_p),
+        ("gstart", C.c_void_p),
+        ("ginfo", C.c_void_p),
+        ("rec_cap", C.c_int64),
+        ("group_cap", C.c_int64),
+        ("stride", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
 EXPORTS = [
     "perm_est_create",
     "perm_est_create_batch",
@@ -68,12 +81,22 @@ EXPORTS = [
     "perm_est_run",
     "perm_est_run_range",
     "perm_est_run_batch",
+    "perm_est_set_model",
+    "perm_est_record",
+    "perm_est_mlp_create",
+    "perm_est_mlp_get_params",
+    "perm_est_mlp_forward",
+    "perm_est_mlp_loss_grad",
+    "perm_est_mlp_train",
+    "perm_est_mlp_destroy",
     "perm_est_destroy",
     "perm_est_last_error",
 ]
 
 PE_FLAG_FORCE_HBM = 1
 PE_RUN_AUTOTUNE = 1
+PE_SK_LEARNED = 4
+PE_MLP_NPARAM = 4801
 
 _lib = None
 
@@ -102,6 +125,24 @@ def load():
     L.perm_est_create_batch.restype = C.c_int
     L.perm_est_run_batch.argtypes = [P, P, C.c_uint64, C.POINTER(Schedule), P, P, P, P, C.c_int32, P]
     L.perm_est_run_batch.restype = C.c_int
+    L.perm_est_set_model.argtypes = [P, P, C.c_double, P]
+    L.perm_est_set_model.restype = C.c_int
+    L.perm_est_record.argtypes = [P, P, C.c_uint64, C.POINTER(Schedule), C.POINTER(RecordBuffers), P,
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), P]
+    L.perm_est_record.restype = C.c_int
+    L.perm_est_mlp_create.argtypes = [C.c_int32, P, C.POINTER(P)]
+    L.perm_est_mlp_create.restype = C.c_int
+    L.perm_est_mlp_get_params.argtypes = [P, P, P]
+    L.perm_est_mlp_get_params.restype = C.c_int
+    L.perm_est_mlp_forward.argtypes = [P, P, C.c_int64, P, P]
+    L.perm_est_mlp_forward.restype = C.c_int
+    L.perm_est_mlp_loss_grad.argtypes = [P, P, P, P, P, C.c_int64, C.c_int64, C.POINTER(C.c_double), P, P]
+    L.perm_est_mlp_loss_grad.restype = C.c_int
+    L.perm_est_mlp_train.argtypes = [P, P, P, P, P, C.c_int64, C.c_int32, C.c_int64, C.c_double, C.c_uint64,
+                                     P, P]
+    L.perm_est_mlp_train.restype = C.c_int
+    L.perm_est_mlp_destroy.argtypes = [P]
+    L.perm_est_mlp_destroy.restype = None
     L.perm_est_destroy.argtypes = [P]
     L.perm_est_destroy.restype = None
     L.perm_est_last_error.argtypes = []

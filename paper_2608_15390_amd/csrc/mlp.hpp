@@ -16,6 +16,7 @@
 namespace pe {
 
 constexpr int kIn = 8, kH = 64;
+constexpr int kEtabN = 2048;  // entries of the integer softmax table (larger gaps weigh 0)
 constexpr int kNParam = kIn * kH + kH + kH * kH + kH + kH + 1;  // 4801
 // offsets into the packed parameter vector
 constexpr int kOffW1 = 0, kOffB1 = kIn * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
@@ -168,32 +169,41 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *P, const float
     }
 }
 
-// per group: softmax, d loss / d logit = (softmax - target) / G, loss
+// Per group g in [g0, g1): softmax of its logits, d loss / d logit =
+// (softmax - target) / G and the group's cross-entropy added to *loss.
+// Records are indexed relative to r0 = gstart[g0] (the window's first).
 __global__ void k_softmax_xent(const float *logits, const float *targets, const int64_t *gstart,
-                               const int32_t *glen, int64_t g0, int64_t g1, int64_t G, float *dlogits,
-                               double *loss) {
+                               const int32_t *ginfo, int64_t g0, int64_t g1, float *dlogits, double *loss) {
     const int64_t g = g0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= g1) return;
-    const int64_t s = gstart[g];
-    const int32_t k = glen[g];
-    float mx = -3.0e38f;
-    for (int32_t i = 0; i < k; ++i) mx = fmaxf(mx, logits[s + i]);
-    float sum = 0.0f;
-    for (int32_t i = 0; i < k; ++i) sum += expf(logits[s + i] - mx);
     double lg = 0.0;
-    for (int32_t i = 0; i < k; ++i) {
-        const float p = expf(logits[s + i] - mx) / sum;
-        const float y = targets[s + i];
-        dlogits[s + i] = (p - y) / (float)G;
-        if (y > 0.0f) lg -= (double)y * log((double)p > 1e-30 ? (double)p : 1e-30);
+    if (g < g1) {
+        const int64_t s = gstart[g] - gstart[g0];
+        const int32_t k = ginfo[4 * g];
+        const float inv_g = 1.0f / (float)(g1 - g0);
+        float mx = -3.0e38f;
+        for (int32_t i = 0; i < k; ++i) mx = fmaxf(mx, logits[s + i]);
+        float sum = 0.0f;
+        for (int32_t i = 0; i < k; ++i) sum += expf(logits[s + i] - mx);
+        for (int32_t i = 0; i < k; ++i) {
+            const float p = expf(logits[s + i] - mx) / sum;
+            const float y = targets[gstart[g0] + s + i];
+            dlogits[s + i] = (p - y) * inv_g;
+            if (y > 0.0f) lg -= (double)y * ((double)(logits[s + i] - mx) - log((double)sum));
+        }
+        lg /= (double)(g1 - g0);
     }
-    atomicAdd(loss, lg / (double)G);
+    // one atomic per wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o);
+    if (lane_id() == 0) atomicAdd(loss, lg);
 }
 
-// Backward over records [r0, r1): gradients of all parameters, accumulated
-// per wave in registers and added to grad[] once.
+// Backward over the n records of X (dlogits indexed alike): gradients of
+// all parameters, accumulated per wave in registers and stored as that
+// wave's partial, parts[global wave][kNParam] (summed in a fixed order by
+// the caller, so gradients are reproducible).
 __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const float *X, const float *dlogits,
-                                                      int64_t r0, int64_t r1, float *grad) {
+                                                      int64_t n, float *parts) {
     __shared__ MlpLds W;
     __shared__ TileLds tiles[4];
     stage_weights(&W, P);
@@ -209,18 +219,17 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const floa
 #pragma unroll
         for (int b = 0; b < 4; ++b) gW2[a][b] = f32x4{0, 0, 0, 0};
     }
-    const int64_t n = r1 - r0;
     const int64_t tiles_total = (n + 15) / 16;
     for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles_total; t += (int64_t)gridDim.x * 4) {
-        const int64_t base = r0 + 16 * t;
+        const int64_t base = 16 * t;
         f32x4 z1[4], z2[4];
         float lg[4];
-        mlp_tile_forward<false>(&W, T, load_x_tile(X, r1, base), z1, z2, lg);
+        mlp_tile_forward<false>(&W, T, load_x_tile(X, n, base), z1, z2, lg);
         float dl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t row = base + q0 + j;
-            dl[j] = row < r1 ? dlogits[row] : 0.0f;
+            dl[j] = row < n ? dlogits[row] : 0.0f;
             if (c0 == 0) gb3 += dl[j];
         }
         // dZ2 = dl w3 1[z2 > 0]; gradients of w3, b2; dW2 = H1^T dZ2
@@ -281,25 +290,26 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const floa
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t row = base + q0 + j;
-            xt[j] = (row < r1 && c0 < kIn) ? to_bf16(X[row * kIn + c0]) : (short)0;
+            xt[j] = (row < n && c0 < kIn) ? to_bf16(X[row * kIn + c0]) : (short)0;
         }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) gW1[nt] = mfma16(xt, dz1b[nt], gW1[nt]);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     }
-    // fold the per-lane partial sums into grad[]
+    // this wave's partial: every parameter written by exactly one lane
+    float *grad = parts + ((size_t)blockIdx.x * 4 + wave) * kNParam;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                atomicAdd(&grad[kOffW2 + (16 * mt + q0 + j) * kH + 16 * nt + c0], gW2[mt][nt][j]);
+                grad[kOffW2 + (16 * mt + q0 + j) * kH + 16 * nt + c0] = gW2[mt][nt][j];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (q0 + j < kIn) atomicAdd(&grad[kOffW1 + (q0 + j) * kH + 16 * nt + c0], gW1[nt][j]);
+            if (q0 + j < kIn) grad[kOffW1 + (q0 + j) * kH + 16 * nt + c0] = gW1[nt][j];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         float a = gb1[nt], b = gb2[nt], c = gw3[nt];
@@ -307,14 +317,14 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const floa
         b += __shfl_xor(b, 16); b += __shfl_xor(b, 32);
         c += __shfl_xor(c, 16); c += __shfl_xor(c, 32);
         if (l < 16) {
-            atomicAdd(&grad[kOffB1 + 16 * nt + c0], a);
-            atomicAdd(&grad[kOffB2 + 16 * nt + c0], b);
-            atomicAdd(&grad[kOffW3 + 16 * nt + c0], c);
+            grad[kOffB1 + 16 * nt + c0] = a;
+            grad[kOffB2 + 16 * nt + c0] = b;
+            grad[kOffW3 + 16 * nt + c0] = c;
         }
     }
     float s3 = gb3;
     for (int o = 32; o > 0; o >>= 1) s3 += __shfl_xor(s3, o);
-    if (l == 0) atomicAdd(&grad[kOffB3], s3);
+    if (l == 0) grad[kOffB3] = s3;
 }
 
 __global__ void k_adam(float *P, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
@@ -331,6 +341,24 @@ __global__ void k_adam(float *P, const float *g, float *m, float *v, int n, floa
 __global__ void k_fill_f32n(int64_t n, float *p, float v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Inference grid of the learned proposal: every parameter snapped to the
+// nearest multiple of 1/64 in [-127/64, 127/64]; *bad set for non-finite input.
+__global__ void k_quantize_params(const float *src, float *dst, int n, int32_t *bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float p = src[i];
+    if (!__builtin_isfinite(p)) { atomicOr(bad, 1); dst[i] = 0.0f; return; }
+    float k = rintf(p * 64.0f);
+    k = k < -127.0f ? -127.0f : (k > 127.0f ? 127.0f : k);
+    dst[i] = k * (1.0f / 64.0f);
+}
+
+// integer softmax table E[d] = rint(2^24 exp(-d/16)), d = 0 .. kEtabN-1
+__global__ void k_etab(int64_t *E) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < kEtabN) E[d] = (int64_t)rint(16777216.0 * exp(-(double)d / 16.0));
 }
 
 }  // namespace pe

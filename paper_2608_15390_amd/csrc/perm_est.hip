@@ -132,6 +132,12 @@ struct perm_est {
     int32_t *tmp_counters = nullptr;
     int64_t tmp_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // learned proposal: snapped network parameters and the softmax table
+    float *mlp = nullptr;
+    int64_t *etab = nullptr;
+    double mix_alpha = 0.05;
+    bool has_model = false;
+    unsigned long long *rec_ctr = nullptr;  // [0] claimed, [1] written (records << 32 | groups)
     // host copies the async uploads read from
     std::vector<TrajArgs> args_host;
     BatchArgs batch_host{};
@@ -395,14 +401,15 @@ void launch_traj(int sk, bool dm, bool wt, unsigned blocks, unsigned threads, si
         case PE_SK_NONE: launch_dm<kSkNone>(dm, wt, blocks, threads, shmem, s, b); break;
         case PE_SK_FIXED: launch_dm<kSkFixed>(dm, wt, blocks, threads, shmem, s, b); break;
         case PE_SK_ADAPTIVE: launch_dm<kSkAdaptive>(dm, wt, blocks, threads, shmem, s, b); break;
-        default: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, b); break;
+        case PE_SK_LOCAL: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, b); break;
+        default: launch_dm<kSkLearned>(dm, wt, blocks, threads, shmem, s, b); break;
     }
 }
 
 int check_schedule(const perm_est_schedule *s) {
     if (!s) return fail(PE_EINVAL, "schedule is NULL");
     if (s->vertex_rule < 0 || s->vertex_rule > 1) return fail(PE_EINVAL, "bad vertex_rule");
-    if (s->sk_policy < 0 || s->sk_policy > 3) return fail(PE_EINVAL, "bad sk_policy");
+    if (s->sk_policy < 0 || s->sk_policy > 4) return fail(PE_EINVAL, "bad sk_policy");
     if (s->dm_policy < 0 || s->dm_policy > 3) return fail(PE_EINVAL, "bad dm_policy");
     if (s->initial_dm < 0 || s->initial_dm > 1) return fail(PE_EINVAL, "bad initial_dm");
     if (s->K0 < 0 || s->K < 0) return fail(PE_EINVAL, "K0 and K must be >= 0");
@@ -468,7 +475,7 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
         h->cu_count = cus;
     int rc;
     if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, 5)) || (rc = dalloc(&h->flags, 8)) ||
-        (rc = dalloc(&h->batch_dev, 1)))
+        (rc = dalloc(&h->batch_dev, 1)) || (rc = dalloc(&h->rec_ctr, 2)))
         return rc;
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
         return fail(PE_EDEVICE, "hipEventCreate failed");
@@ -511,14 +518,17 @@ int grow_mats(perm_est *h, size_t count) {
 }
 
 // one persistent launch over every matrix's trajectories + per-matrix
-// reductions.  tune_only: time the launch shape (wpb, per_cu) instead of
-// producing results (outputs go to scratch buffers).
+// reductions.  res == nullptr: only time the launch shape (wpb, per_cu);
+// outputs go to scratch buffers.  rec: training-pair recording, or nullptr.
 int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vector<RunPart> &parts,
-           perm_est_result *res, hipStream_t s, int wpb_req, int per_cu_req, double *elapsed_ms) {
+           perm_est_result *res, hipStream_t s, int wpb_req, int per_cu_req, double *elapsed_ms,
+           const perm_est_record_buffers *rec = nullptr) {
     const size_t count = h->mats.size();
     int rc;
     if ((rc = grow_mats(h, count))) return rc;
-    const bool own_rc = sched->sk_policy != PE_SK_NONE;
+    const bool learned = sched->sk_policy == PE_SK_LEARNED;
+    if (learned && !h->has_model) return fail(PE_EINVAL, "PE_SK_LEARNED needs perm_est_set_model first");
+    const bool own_rc = sched->sk_policy != PE_SK_NONE && !learned;
     const bool local = sched->sk_policy == PE_SK_LOCAL;
     const bool dm = sched->dm_policy != PE_DM_NONE;
     const bool wt = h->mats[0].weighted;
@@ -585,7 +595,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.sk_policy = sched->sk_policy;
         a.dm_policy = sched->dm_policy;
         a.K = sched->K;
-        a.scaled = (P->r0 != nullptr) || own_rc;
+        a.scaled = !learned && ((P->r0 != nullptr) || own_rc);
         a.theta_th = sched->theta_th;
         a.theta_tr = sched->theta_tr;
         a.seed = seed;
@@ -598,6 +608,20 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.path_hash = parts[b].path_hash;
         a.path = parts[b].path;
         a.err = h->work + 1;
+        a.mlp = learned ? h->mlp : nullptr;
+        a.etab = learned ? h->etab : nullptr;
+        a.mix_alpha = h->mix_alpha;
+        if (rec) {
+            a.rec_x = rec->x;
+            a.rec_y = rec->y;
+            a.rec_gstart = rec->gstart;
+            a.rec_ginfo = rec->ginfo;
+            a.rec_counter = h->rec_ctr;
+            a.rec_written = h->rec_ctr + 1;
+            a.rec_cap = rec->rec_cap;
+            a.rec_gcap = rec->group_cap;
+            a.rec_stride = rec->stride;
+        }
         tmp_off += parts[b].count;
     }
     // processing order: most expensive matrices first (n * m per trajectory)
@@ -613,9 +637,10 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     for (size_t b = 0; b < count; ++b) h->seg_host[2 * b + 1] = parts[b].count;
 
     // ---- tier and launch shape
-    const size_t tree_bytes = (size_t)tree_total * 4;
+    const size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
     const size_t kLdsBlock = 64 * 1024, kLdsCU = 160 * 1024;
     const bool lds = tree_bytes + state_bytes <= 32 * 1024 && !(h->opt_flags & PE_FLAG_FORCE_HBM);
+    static_assert(kMlpBlockBytes % 16 == 0 && kMlpWaveBytes % 16 == 0, "LDS carve-outs keep 16-byte alignment");
     BatchArgs &B = h->batch_host;
     B = BatchArgs{};
     B.mats = h->args_dev;
@@ -626,10 +651,14 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.work_next = h->work;
     B.work_totals = h->work_totals;
     B.lds_tree_bytes = (int32_t)tree_bytes;
+    B.lds_mlp_bytes = learned ? kMlpWaveBytes : 0;
+    B.mlp = learned ? h->mlp : nullptr;
+    const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     int wpb = wpb_req > 0 ? wpb_req : 4;
-    size_t per_wave = tree_bytes + (lds ? state_bytes : 0);
-    wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, kLdsBlock / std::max<size_t>(per_wave, 1)));
-    const size_t shmem = (size_t)wpb * per_wave;
+    size_t per_wave = tree_bytes + (size_t)B.lds_mlp_bytes + (lds ? state_bytes : 0);
+    wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
+    const size_t shmem = block_fixed + (size_t)wpb * per_wave;
+    if (shmem > kLdsBlock) return fail(PE_ENOTSUP, "per-trajectory LDS need exceeds one block's LDS");
     size_t per_cu = per_cu_req > 0 ? (size_t)per_cu_req : std::max<size_t>(1, 16 / wpb);
     per_cu = std::max<size_t>(1, std::min<size_t>(per_cu, kLdsCU / std::max<size_t>(shmem, 1)));
     const unsigned blocks = (unsigned)std::max<int64_t>(
@@ -660,6 +689,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
     k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
     k_fill_i32<<<1, 64, 0, s>>>(10, reinterpret_cast<int32_t *>(h->work_totals), 0);
+    if (rec) k_fill_i32<<<1, 64, 0, s>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
     PE_HIP(hipEventRecord(h->ev0, s));
     launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, s, h->batch_dev);
     PE_HIP(hipGetLastError());
@@ -751,6 +781,100 @@ int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, cons
     return PE_OK;
 }
 
+// true when p is device (or managed) memory of the current device
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    (void)hipGetLastError();  // a host pointer leaves an error behind: clear it
+    if (e != hipSuccess) return false;
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+// trainer of the proposal network (declared opaque in the header)
+struct perm_est_mlp {
+    int device = 0;
+    float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    float *logits = nullptr, *dl = nullptr, *parts = nullptr;
+    int64_t ws_cap = 0;
+    double *loss = nullptr;
+    int64_t step = 0;
+};
+
+namespace {
+
+constexpr int kMlpMaxWaves = 1024;  // backward: one parameter-sized partial per wave
+
+int mlp_grow(perm_est_mlp *t, int64_t n) {
+    if (t->ws_cap >= n) return PE_OK;
+    dfree(t->logits); dfree(t->dl);
+    t->ws_cap = 0;
+    int rc;
+    const int64_t cap = std::max<int64_t>(n, 4096);
+    if ((rc = dalloc(&t->logits, cap)) || (rc = dalloc(&t->dl, cap))) return rc;
+    t->ws_cap = cap;
+    return PE_OK;
+}
+
+__global__ void k_sum_parts(const float *parts, int nparts, float *grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParam) return;
+    float acc = 0.0f;
+    for (int w = 0; w < nparts; ++w) acc += parts[(size_t)w * kNParam + i];
+    grad[i] = acc;
+}
+
+// loss (added to *loss_dev) and gradient (into grad) of groups [g0, g1)
+// whose records are [r0, r0 + n)
+int mlp_window(perm_est_mlp *t, const float *x, const float *y, const int64_t *gstart, const int32_t *ginfo,
+               int64_t g0, int64_t g1, int64_t r0, int64_t n, float *grad, hipStream_t s) {
+    int rc;
+    if ((rc = mlp_grow(t, n))) return rc;
+    const float *xw = x + r0 * kIn;
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned fblocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
+    k_mlp_forward<<<fblocks, 256, 0, s>>>(t->P, xw, n, t->logits);
+    k_softmax_xent<<<blocks_for(g1 - g0), 256, 0, s>>>(t->logits, y, gstart, ginfo, g0, g1, t->dl, t->loss);
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(tiles, kMlpMaxWaves));
+    const unsigned bblocks = (unsigned)((waves + 3) / 4);
+    k_mlp_backward<<<bblocks, 256, 0, s>>>(t->P, xw, t->dl, n, t->parts);
+    k_sum_parts<<<blocks_for(kNParam), 256, 0, s>>>(t->parts, (int)bblocks * 4, grad);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+// copy the group table [g0, g1) to the host and check that the groups are
+// non-empty and tile one contiguous range of records
+int load_groups(const int64_t *gstart, const int32_t *ginfo, int64_t g0, int64_t g1, hipStream_t s,
+                std::vector<int64_t> &gs, std::vector<int32_t> &gi) {
+    const int64_t G = g1 - g0;
+    gs.resize(G);
+    gi.resize(4 * G);
+    PE_HIP(hipMemcpyAsync(gs.data(), gstart + g0, sizeof(int64_t) * G, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(gi.data(), ginfo + 4 * g0, sizeof(int32_t) * 4 * G, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    if (gs[0] < 0) return fail(PE_EINVAL, "negative record offset");
+    for (int64_t g = 0; g < G; ++g) {
+        if (gi[4 * g] < 1) return fail(PE_EINVAL, "empty group");
+        if (g > 0 && gs[g] != gs[g - 1] + gi[4 * (g - 1)])
+            return fail(PE_EINVAL, "groups are not contiguous records");
+    }
+    return PE_OK;
+}
+
+int mlp_adam(perm_est_mlp *t, double lr, hipStream_t s) {
+    t->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)t->step));
+    const float c2 = (float)(1.0 - std::pow(b2, (double)t->step));
+    k_adam<<<blocks_for(kNParam), 256, 0, s>>>(t->P, t->grad, t->m, t->v, kNParam, (float)lr, (float)b1, (float)b2,
+                                               1e-8f, c1, c2);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -784,6 +908,10 @@ int perm_est_schedule_preset(const char *name, perm_est_schedule *out) {
         paper(PE_SK_LOCAL, PE_DM_TRCK);
     } else if (nm == "local_nodm") {
         paper(PE_SK_LOCAL, PE_DM_NONE);
+    } else if (nm == "learned") {
+        paper(PE_SK_LEARNED, PE_DM_NONE);
+    } else if (nm == "learned_threshold") {
+        paper(PE_SK_LEARNED, PE_DM_THRS);
     } else {
         return fail(PE_EINVAL, "unknown preset '" + nm + "'");
     }
@@ -842,6 +970,7 @@ void perm_est_destroy(perm_est_t *h) {
     dfree(h->hbm_state); dfree(h->work); dfree(h->work_totals); dfree(h->flags); dfree(h->batch_dev);
     dfree(h->args_dev); dfree(h->order_dev); dfree(h->item_off_dev); dfree(h->seg_dev); dfree(h->stats);
     dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
+    dfree(h->mlp); dfree(h->etab); dfree(h->rec_ctr);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -895,6 +1024,186 @@ int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed, cons
     if (flags & PE_RUN_AUTOTUNE)
         if ((rc = tuned_shape(h, sched, seed, parts, s, &wpb, &per_cu))) return rc;
     return launch(h, sched, seed, parts, res, s, wpb, per_cu, nullptr);
+}
+
+int perm_est_set_model(perm_est_t *h, const float *params, double mix_alpha, void *stream) {
+    if (!h) return fail(PE_EINVAL, "null handle");
+    if (!(mix_alpha >= 0.0 && mix_alpha <= 1.0)) return fail(PE_EINVAL, "mix_alpha must lie in [0, 1]");
+    PE_HIP(hipSetDevice(h->device));
+    if (!is_device_ptr(params)) return fail(PE_EINVAL, "params must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (!h->mlp && (rc = dalloc(&h->mlp, kNParam))) return rc;
+    if (!h->etab && (rc = dalloc(&h->etab, kEtabN))) return rc;
+    if ((rc = zero_flag(h->flags, s))) return rc;
+    k_quantize_params<<<blocks_for(kNParam), 256, 0, s>>>(params, h->mlp, kNParam, h->flags);
+    k_etab<<<blocks_for(kEtabN), 256, 0, s>>>(h->etab);
+    PE_HIP(hipGetLastError());
+    int32_t bad = 0;
+    if ((rc = read_flag(h->flags, &bad, s))) return rc;
+    if (bad) {
+        h->has_model = false;
+        return fail(PE_EINVAL, "params hold a non-finite value");
+    }
+    h->mix_alpha = mix_alpha;
+    h->has_model = true;
+    return PE_OK;
+}
+
+int perm_est_record(perm_est_t *h, const int64_t *n_traj, uint64_t seed, const perm_est_schedule *sched,
+                    const perm_est_record_buffers *buf, perm_est_result *res, int64_t *n_records,
+                    int64_t *n_groups, void *stream) {
+    if (!h || !res || !n_traj || !buf || !n_records || !n_groups)
+        return fail(PE_EINVAL, "null handle, n_traj, buffers, result or count outputs");
+    int rc;
+    if ((rc = check_schedule(sched))) return rc;
+    if (sched->sk_policy == PE_SK_LEARNED) return fail(PE_EINVAL, "recording needs a scaling-based schedule");
+    if (buf->rec_cap < 2 || buf->rec_cap >= ((int64_t)1 << 31) || buf->group_cap < 1 ||
+        buf->group_cap >= ((int64_t)1 << 31) || buf->stride < 1 || buf->reserved != 0)
+        return fail(PE_EINVAL, "bad record capacities or stride");
+    if ((reinterpret_cast<uintptr_t>(buf->x) & 15) != 0) return fail(PE_EINVAL, "x must be 16-byte aligned");
+    PE_HIP(hipSetDevice(h->device));
+    if (!is_device_ptr(buf->x) || !is_device_ptr(buf->y) || !is_device_ptr(buf->gstart) ||
+        !is_device_ptr(buf->ginfo))
+        return fail(PE_EINVAL, "record buffers must be device memory");
+    const size_t count = h->mats.size();
+    std::vector<RunPart> parts(count);
+    for (size_t b = 0; b < count; ++b) {
+        if (n_traj[b] < 1 || n_traj[b] >= ((int64_t)1 << 32))
+            return fail(PE_EINVAL, "every matrix needs 1 <= n_traj < 2^32");
+        parts[b].count = n_traj[b];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = launch(h, sched, seed, parts, res, s, 0, 0, nullptr, buf))) return rc;
+    unsigned long long written = 0;
+    PE_HIP(hipMemcpyAsync(&written, h->rec_ctr + 1, sizeof(written), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    *n_records = (int64_t)(written >> 32);
+    *n_groups = (int64_t)(written & 0xFFFFFFFFull);
+    return PE_OK;
+}
+
+int perm_est_mlp_create(int32_t device, const float *params, perm_est_mlp_t **out) {
+    if (!out) return fail(PE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params) return fail(PE_EINVAL, "params is NULL");
+    for (int i = 0; i < kNParam; ++i)
+        if (!std::isfinite(params[i])) return fail(PE_EINVAL, "params hold a non-finite value");
+    perm_est_mlp *t = new (std::nothrow) perm_est_mlp();
+    if (!t) return fail(PE_ENOMEM, "host allocation failed");
+    t->device = device;
+    int rc = PE_OK;
+    auto setup = [&]() -> int {
+        PE_HIP(hipSetDevice(device));
+        int r;
+        if ((r = dalloc(&t->P, kNParam)) || (r = dalloc(&t->m, kNParam)) || (r = dalloc(&t->v, kNParam)) ||
+            (r = dalloc(&t->grad, kNParam)) || (r = dalloc(&t->loss, 1)) ||
+            (r = dalloc(&t->parts, (size_t)kMlpMaxWaves * kNParam)))
+            return r;
+        PE_HIP(hipMemcpy(t->P, params, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+        PE_HIP(hipMemset(t->m, 0, sizeof(float) * kNParam));
+        PE_HIP(hipMemset(t->v, 0, sizeof(float) * kNParam));
+        return PE_OK;
+    };
+    if ((rc = setup())) { perm_est_mlp_destroy(t); return rc; }
+    *out = t;
+    return PE_OK;
+}
+
+int perm_est_mlp_get_params(perm_est_mlp_t *t, float *out, void *stream) {
+    if (!t || !out) return fail(PE_EINVAL, "null trainer or output");
+    PE_HIP(hipSetDevice(t->device));
+    hipStream_t s = (hipStream_t)stream;
+    PE_HIP(hipMemcpyAsync(out, t->P, sizeof(float) * kNParam, hipMemcpyDefault, s));
+    PE_HIP(hipStreamSynchronize(s));
+    return PE_OK;
+}
+
+int perm_est_mlp_forward(perm_est_mlp_t *t, const float *x, int64_t n, float *logits, void *stream) {
+    if (!t || n < 0 || (n > 0 && (!x || !logits))) return fail(PE_EINVAL, "bad trainer, n or pointers");
+    if (n == 0) return PE_OK;
+    PE_HIP(hipSetDevice(t->device));
+    if (!is_device_ptr(x) || !is_device_ptr(logits)) return fail(PE_EINVAL, "x and logits must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
+    k_mlp_forward<<<blocks, 256, 0, s>>>(t->P, x, n, logits);
+    PE_HIP(hipGetLastError());
+    PE_HIP(hipStreamSynchronize(s));
+    return PE_OK;
+}
+
+int perm_est_mlp_loss_grad(perm_est_mlp_t *t, const float *x, const float *y, const int64_t *gstart,
+                           const int32_t *ginfo, int64_t g0, int64_t g1, double *loss, float *grad,
+                           void *stream) {
+    if (!t || !x || !y || !gstart || !ginfo || !loss) return fail(PE_EINVAL, "null argument");
+    if (g0 < 0 || g1 <= g0) return fail(PE_EINVAL, "empty or negative group window");
+    PE_HIP(hipSetDevice(t->device));
+    if (!is_device_ptr(x) || !is_device_ptr(y) || !is_device_ptr(gstart) || !is_device_ptr(ginfo) ||
+        (grad && !is_device_ptr(grad)))
+        return fail(PE_EINVAL, "recording arrays and grad must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> gs;
+    std::vector<int32_t> gi;
+    int rc;
+    if ((rc = load_groups(gstart, ginfo, g0, g1, s, gs, gi))) return rc;
+    const int64_t first = gs.front(), n = gs.back() + gi[gi.size() - 4] - first;
+    k_fill_f32n<<<1, 64, 0, s>>>(2, reinterpret_cast<float *>(t->loss), 0.0f);
+    if ((rc = mlp_window(t, x, y, gstart, ginfo, g0, g1, first, n, grad ? grad : t->grad, s))) return rc;
+    PE_HIP(hipMemcpyAsync(loss, t->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    return PE_OK;
+}
+
+int perm_est_mlp_train(perm_est_mlp_t *t, const float *x, const float *y, const int64_t *gstart,
+                       const int32_t *ginfo, int64_t n_groups, int32_t epochs, int64_t batch_groups,
+                       double lr, uint64_t seed, double *loss_per_epoch, void *stream) {
+    if (!t || !x || !y || !gstart || !ginfo) return fail(PE_EINVAL, "null argument");
+    if (n_groups < 1 || epochs < 0 || batch_groups < 1 || !(lr > 0.0) || !std::isfinite(lr))
+        return fail(PE_EINVAL, "bad n_groups, epochs, batch_groups or lr");
+    PE_HIP(hipSetDevice(t->device));
+    if (!is_device_ptr(x) || !is_device_ptr(y) || !is_device_ptr(gstart) || !is_device_ptr(ginfo))
+        return fail(PE_EINVAL, "recording arrays must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    // window bounds from the group table (one copy)
+    std::vector<int64_t> gs;
+    std::vector<int32_t> gi;
+    int rc;
+    if ((rc = load_groups(gstart, ginfo, 0, n_groups, s, gs, gi))) return rc;
+    const int64_t nwin = (n_groups + batch_groups - 1) / batch_groups;
+    std::vector<int64_t> order(nwin);
+    for (int64_t w = 0; w < nwin; ++w) order[w] = w;
+    uint64_t rs = seed;
+    auto next = [&]() {  // SplitMix64 stream for the window shuffle
+        uint64_t z = (rs += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (int32_t ep = 0; ep < epochs; ++ep) {
+        for (int64_t w = nwin - 1; w > 0; --w) std::swap(order[w], order[(int64_t)(next() % (uint64_t)(w + 1))]);
+        k_fill_f32n<<<1, 64, 0, s>>>(2, reinterpret_cast<float *>(t->loss), 0.0f);
+        for (int64_t w : order) {
+            const int64_t g0 = w * batch_groups, g1 = std::min<int64_t>(n_groups, g0 + batch_groups);
+            const int64_t r0 = gs[g0], n = gs[g1 - 1] + gi[4 * (g1 - 1)] - r0;
+            if ((rc = mlp_window(t, x, y, gstart, ginfo, g0, g1, r0, n, t->grad, s))) return rc;
+            if ((rc = mlp_adam(t, lr, s))) return rc;
+        }
+        double ls = 0.0;
+        PE_HIP(hipMemcpyAsync(&ls, t->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+        PE_HIP(hipStreamSynchronize(s));
+        if (loss_per_epoch) loss_per_epoch[ep] = ls / (double)nwin;
+    }
+    PE_HIP(hipStreamSynchronize(s));
+    return PE_OK;
+}
+
+void perm_est_mlp_destroy(perm_est_mlp_t *t) {
+    if (!t) return;
+    (void)hipSetDevice(t->device);
+    dfree(t->P); dfree(t->m); dfree(t->v); dfree(t->grad); dfree(t->logits); dfree(t->dl); dfree(t->parts);
+    dfree(t->loss);
+    delete t;
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@
 // minimum degree with the smallest id.
 #pragma once
 #include "device.hpp"
+#include "mlp.hpp"
 
 namespace pe {
 
@@ -52,7 +53,7 @@ struct Rec {
     int32_t stamp;  // (step + 1) << 6 | lane of the last local-repair visit
 };
 
-enum : int32_t { kSkNone = 0, kSkFixed = 1, kSkAdaptive = 2, kSkLocal = 3 };
+enum : int32_t { kSkNone = 0, kSkFixed = 1, kSkAdaptive = 2, kSkLocal = 3, kSkLearned = 4 };
 enum : int32_t { kDmNone = 0, kDmAll = 1, kDmThrs = 2, kDmTrck = 3 };
 
 struct TrajArgs {
@@ -78,6 +79,21 @@ struct TrajArgs {
     int32_t *path;             // [count][2n] or nullptr
     int32_t *counters;         // [count][4] or nullptr
     uint32_t *err;             // internal-consistency error bits (zeroed before launch)
+    // learned proposal: network parameters on the inference grid, softmax table
+    const float *mlp;
+    const int64_t *etab;
+    double mix_alpha;
+    // training-pair recording (nullptr = off): every rec_stride-th step with at
+    // least two candidates and a list of at most one wave writes the
+    // candidates' features and the current proposal as one group
+    float *rec_x;              // [rec_cap][8]
+    float *rec_y;              // [rec_cap]
+    int64_t *rec_gstart;       // [rec_gcap] first record of the group
+    int32_t *rec_ginfo;        // [rec_gcap][4] = {length, matrix b, trajectory k, step t}
+    unsigned long long *rec_counter;  // claimed (records << 32) | groups
+    unsigned long long *rec_written;  // written (records << 32) | groups
+    int64_t rec_cap, rec_gcap;
+    int32_t rec_stride;
 };
 
 // ------------------------------------------------------------------ views
@@ -661,10 +677,78 @@ __device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t
 }
 
 // ------------------------------------------------------------------ kernel
+template <int SK>
+struct OwnRC { static constexpr bool value = SK == kSkFixed || SK == kSkAdaptive || SK == kSkLocal; };
+
+// features of the candidate edge of Eq. (q) for the learned proposal (see
+// the definition in the oracle): exact operations only
+__device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uint32_t deg_gam, float r0_rho,
+                                                 float c0_gam, int32_t t, int32_t n, bool v_row) {
+    auto q64 = [](double y) -> float {
+        double k = rint(y * 64.0);
+        k = k < -256.0 ? -256.0 : (k > 255.0 ? 255.0 : k);
+        return (float)(k / 64.0);
+    };
+    auto plog2 = [](double s) -> double {
+        int e;
+        const double m = frexp(s, &e);
+        return (double)e - 2.0 + 2.0 * m;
+    };
+    x[0] = (float)(deg_rho < 255u ? deg_rho : 255u) / 64.0f;
+    x[1] = (float)(deg_gam < 255u ? deg_gam : 255u) / 64.0f;
+    x[2] = q64(plog2((double)r0_rho) / 4.0);
+    x[3] = q64(plog2((double)c0_gam) / 4.0);
+    x[4] = q64((double)t / (double)n);
+    x[5] = v_row ? 1.0f : 0.0f;
+    x[6] = 0.0f;
+    x[7] = 0.0f;
+}
+
+// Logits (units of 1/16) of the candidates held by the lanes of one list
+// chunk: features staged in LDS, the quantised network on matrix cores in
+// 16-lane tiles.  Lanes without a candidate return 0.
+__device__ int32_t learned_logits(const MlpLds *W, char *scratch, bool cand, uint32_t deg_rho,
+                                  uint32_t deg_gam, float r0_rho, float c0_gam, int32_t t, int32_t n,
+                                  bool v_row, int32_t chunk_len) {
+    const int l = lane_id();
+    float *feat = reinterpret_cast<float *>(scratch);                    // [64][8]
+    int32_t *logit = reinterpret_cast<int32_t *>(scratch + 64 * 8 * 4);  // [64]
+    TileLds *tile = reinterpret_cast<TileLds *>(scratch + 64 * 8 * 4 + 64 * 4);
+    float x[8];
+    learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_row);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) feat[l * 8 + k] = cand ? x[k] : 0.0f;
+    wave_fence();
+    const int ntiles = (chunk_len + 15) / 16;
+    for (int ti = 0; ti < ntiles; ++ti) {
+        bf16x4 xa;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * (l / 16) + j;
+            xa[j] = k < kIn ? to_bf16(feat[(16 * ti + l % 16) * 8 + k]) : (short)0;
+        }
+        f32x4 z1[4], z2[4];
+        float lg[4];
+        mlp_tile_forward<true>(W, tile, xa, z1, z2, lg);
+        if (l % 16 == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float L = rintf(lg[j] * 16.0f);
+                L = L < -1024.0f ? -1024.0f : (L > 1023.0f ? 1023.0f : L);
+                logit[16 * ti + 4 * (l / 16) + j] = (int32_t)L;
+            }
+        }
+        wave_fence();
+    }
+    const int32_t mine = cand ? logit[l] : 0;
+    wave_fence();
+    return mine;
+}
+
 template <int SK, bool DM, bool WT>
-__device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<SK != kSkNone, DM, WT> &T,
-                                               int64_t q, Work &work) {
-    constexpr bool OWN = SK != kSkNone;
+__device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT> &T,
+                                               int64_t q, Work &work, const MlpLds *mlpw, char *mlps) {
+    constexpr bool OWN = OwnRC<SK>::value;
     const int l = lane_id();
     const int32_t n = a.A.n;
     const uint32_t k = (uint32_t)(a.first + q);
@@ -741,15 +825,90 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<SK 
             kc = __popcll(ballot(cand));
             if (kc == 0) { alive = false; break; }
             const float s = a.scaled ? bv * sc : bv;
-            const float lmax = (cand && s > 0.0f) ? s : 0.0f;
-            const float smax = wave_max_f32(lmax);
-            const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
             uint64_t w = 0;
-            if (cand) {
-                if (kc == 1 || uniform) w = 1;
-                else {
-                    const float rr = rintf((s / smax) * 16777216.0f);
-                    w = rr >= 1.0f ? (uint64_t)rr : 1ull;
+            if (SK == kSkLearned) {
+                // quantised network logits -> integer softmax table -> uniform mix
+                const uint32_t deg_v = (uint32_t)kc;
+                const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
+                int32_t L = 0;
+                if (kc > 1) {
+                    const float r0r = a.r0 ? a.r0[cand ? rho_c : 0] : 1.0f;
+                    const float c0g = a.c0 ? a.c0[cand ? gam_c - n : 0] : 1.0f;
+                    L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
+                                       t, n, v_row, ve - vb);
+                }
+                int32_t lmx = cand ? L : -2147483647;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const int32_t y2 = __shfl_xor(lmx, o);
+                    lmx = y2 > lmx ? y2 : lmx;
+                }
+                int64_t E = 0;
+                if (cand) {
+                    const int32_t d = lmx - L;
+                    E = d < kEtabN ? a.etab[d] : 0;
+                }
+                const int64_t S = (int64_t)wave_sum_u64((uint64_t)E);
+                if (cand) {
+                    if (kc == 1) w = 1;
+                    else {
+                        const double qq = (1.0 - a.mix_alpha) * (double)E / (double)S + a.mix_alpha / (double)kc;
+                        const double rr = rint(16777216.0 * qq);
+                        w = rr >= 1.0 ? (uint64_t)rr : 1ull;
+                    }
+                }
+            } else {
+                const float lmax = (cand && s > 0.0f) ? s : 0.0f;
+                const float smax = wave_max_f32(lmax);
+                const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
+                if (cand) {
+                    if (kc == 1 || uniform) w = 1;
+                    else {
+                        const float rr = rintf((s / smax) * 16777216.0f);
+                        w = rr >= 1.0f ? (uint64_t)rr : 1ull;
+                    }
+                }
+                // training pairs: features and the current scaled proposal.
+                // Records and groups are claimed by one packed atomic, so the
+                // groups that fit are a prefix of the claim order and their
+                // records are contiguous.
+                if (a.rec_x && kc >= 2 && (t % a.rec_stride) == 0) {
+                    const float ssum = wave_sum_f32(cand ? s : 0.0f);
+                    unsigned long long old = 0;
+                    if (l == 0) {
+                        const unsigned long long cur = __hip_atomic_load(a.rec_counter, __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT);
+                        if ((int64_t)(cur >> 32) + kc <= a.rec_cap && (int64_t)(cur & 0xFFFFFFFFull) < a.rec_gcap)
+                            old = atomicAdd(a.rec_counter, ((unsigned long long)kc << 32) | 1ull);
+                        else
+                            old = ~0ull;
+                    }
+                    old = read_lane(old, 0);
+                    const int64_t base = (int64_t)(old >> 32);
+                    const int64_t gid = (int64_t)(old & 0xFFFFFFFFull);
+                    if (old != ~0ull && base + kc <= a.rec_cap && gid < a.rec_gcap) {
+                        const uint64_t cm = ballot(cand);
+                        if (cand) {
+                            const int64_t r = base + rank_below(cm);
+                            const uint32_t deg_v = (uint32_t)kc;
+                            const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
+                            float x[8];
+                            learned_features(x, v_row ? deg_v : cd, v_row ? cd : deg_v,
+                                             a.r0 ? a.r0[rho_c] : 1.0f, a.c0 ? a.c0[gam_c - n] : 1.0f, t, n, v_row);
+                            float4 *xo = reinterpret_cast<float4 *>(a.rec_x + r * 8);
+                            xo[0] = make_float4(x[0], x[1], x[2], x[3]);
+                            xo[1] = make_float4(x[4], x[5], x[6], x[7]);
+                            a.rec_y[r] = ssum > 0.0f ? s / ssum : 1.0f / (float)kc;
+                        }
+                        if (l == 0) {
+                            a.rec_gstart[gid] = base;
+                            a.rec_ginfo[4 * gid + 0] = kc;
+                            a.rec_ginfo[4 * gid + 1] = (int32_t)a.b;
+                            a.rec_ginfo[4 * gid + 2] = (int32_t)k;
+                            a.rec_ginfo[4 * gid + 3] = t;
+                            atomicAdd(a.rec_written, ((unsigned long long)kc << 32) | 1ull);
+                        }
+                    }
                 }
             }
             const uint64_t incl = wave_incl_scan_u64(w);
@@ -787,33 +946,92 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<SK 
             if (kc == 0) { alive = false; break; }
             const float smax = wave_max_f32(lmax);
             const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
-            auto weight_of = [&](int32_t y, float bv) -> uint64_t {
+            // learned: logits of every candidate chunk into lst_b (free here)
+            int32_t lmx = -2147483647;
+            int64_t Ssum = 0;
+            if (SK == kSkLearned && kc > 1) {
+                int32_t idx0 = 0;
+                for (int32_t base = vb; base < ve; base += kWave) {
+                    const int32_t p = base + l;
+                    bool c0 = false;
+                    int32_t y = 0, e = 0;
+                    float bv = 0.0f;
+                    uint32_t dy = 0;
+                    if (p < ve) {
+                        T.entry(v_row, p, y, e, bv);
+                        dy = T.deg[y];
+                        c0 = dy != kRetired && !T.removed(e);
+                    }
+                    const int32_t rho_c = v_row ? v : y, gam_c = v_row ? y : v;
+                    const float r0r = a.r0 ? a.r0[c0 ? rho_c : 0] : 1.0f;
+                    const float c0g = a.c0 ? a.c0[c0 ? gam_c - n : 0] : 1.0f;
+                    const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
+                                                     v_row ? dy : (uint32_t)kc, r0r, c0g, t, n, v_row,
+                                                     min(kWave, ve - base));
+                    const uint64_t msk = ballot(c0);
+                    if (c0) { T.lst_b[idx0 + rank_below(msk)] = L; lmx = L > lmx ? L : lmx; }
+                    idx0 += __popcll(msk);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const int32_t y2 = __shfl_xor(lmx, o);
+                    lmx = y2 > lmx ? y2 : lmx;
+                }
+                wave_fence();
+                uint64_t part = 0;
+                for (int32_t idx = l; idx < kc; idx += kWave) {
+                    const int32_t d = lmx - T.lst_b[idx];
+                    part += d < kEtabN ? (uint64_t)a.etab[d] : 0ull;
+                }
+                Ssum = (int64_t)wave_sum_u64(part);
+            }
+            // ci: the candidate's rank among all candidates (learned logits in lst_b)
+            auto weight_of = [&](int32_t y, float bv, int32_t ci) -> uint64_t {
+                if (SK == kSkLearned) {
+                    if (kc == 1) return 1ull;
+                    const int32_t d = lmx - T.lst_b[ci];
+                    const int64_t E = d < kEtabN ? a.etab[d] : 0;
+                    const double qq = (1.0 - a.mix_alpha) * (double)E / (double)Ssum + a.mix_alpha / (double)kc;
+                    const double rr = rint(16777216.0 * qq);
+                    return rr >= 1.0 ? (uint64_t)rr : 1ull;
+                }
                 if (kc == 1 || uniform) return 1ull;
                 const float s = a.scaled ? bv * T.scale(y) : bv;
                 const float rr = rintf((s / smax) * 16777216.0f);
                 return rr >= 1.0f ? (uint64_t)rr : 1ull;
             };
+            int32_t cbase = 0;
             for (int32_t base = vb; base < ve; base += kWave) {
                 const int32_t p = base + l;
                 uint64_t w = 0;
+                bool c0 = false;
+                int32_t y = 0, e = 0;
+                float bv = 0.0f;
                 if (p < ve) {
-                    int32_t y, e; float bv;
                     T.entry(v_row, p, y, e, bv);
-                    if (T.active(y) && !T.removed(e)) w = weight_of(y, bv);
+                    c0 = T.active(y) && !T.removed(e);
                 }
+                const uint64_t msk = ballot(c0);
+                if (c0) w = weight_of(y, bv, cbase + rank_below(msk));
+                cbase += __popcll(msk);
                 W += wave_sum_u64(w);
             }
             const uint64_t j = kc > 1 ? lemire_from(R0, W, a.seed, k, a.b, (uint32_t)t) : 0ull;
             uint64_t pre = 0;
+            cbase = 0;
             for (int32_t base = vb; base < ve; base += kWave) {
                 const int32_t p = base + l;
                 uint64_t w = 0;
                 int32_t y = 0, e = 0;
                 float bv = 0.0f;
+                bool c0 = false;
                 if (p < ve) {
                     T.entry(v_row, p, y, e, bv);
-                    if (T.active(y) && !T.removed(e)) w = weight_of(y, bv);
+                    c0 = T.active(y) && !T.removed(e);
                 }
+                const uint64_t msk = ballot(c0);
+                if (c0) w = weight_of(y, bv, cbase + rank_below(msk));
+                cbase += __popcll(msk);
                 const uint64_t incl = wave_incl_scan_u64(w) + pre;
                 const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
                 if (hm) {
@@ -843,7 +1061,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<SK 
         }
         const int32_t rho = v_row ? v : u;
         const int32_t gam = v_row ? u : v;  // column vertex id
-        const double z = (double)T.scale(rho) * (double)T.scale(gam);
+        const double z = SK == kSkLearned ? (double)w_u / (double)W : (double)T.scale(rho) * (double)T.scale(gam);
         if (path && l == 0) { path[2 * t] = v; path[2 * t + 1] = u; }
         h = splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);
 
@@ -1033,27 +1251,40 @@ struct BatchArgs {
     char *hbm_state;          // HBM tier: base of per-wave slots; nullptr = LDS tier
     uint64_t hbm_stride;
     int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
+    int32_t lds_mlp_bytes;    // LDS bytes per wave for the network's tiles (learned)
     int32_t lds_state_bytes;  // LDS tier: bytes of state per wave
     int32_t waves_per_block;
+    const float *mlp;         // learned proposal parameters (staged per block), or nullptr
 };
+
+constexpr int kMlpWaveBytes = 64 * 8 * 4 + 64 * 4 + (int)sizeof(TileLds);
+constexpr int kMlpBlockBytes = ((int)sizeof(MlpLds) + 15) / 16 * 16;
 
 // The argument blocks live in device memory (uniform fields become scalar
 // loads; no private copy of a by-value parameter is needed).
 template <int SK, bool DM, bool WT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || !DM) ? 4 : 1, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || (!DM && SK != kSkLearned)) ? 4 : 1, 8)))
 traj_kernel(const BatchArgs *__restrict__ bp) {
     const BatchArgs &B = *bp;
     extern __shared__ __align__(16) char smem[];
     const int wave = threadIdx.x / kWave;
-    const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_state_bytes;
-    char *mine = smem + (size_t)wave * per_wave;
+    // block: [network weights (learned)] then per wave [tree | network tiles | state]
+    MlpLds *mlpw = reinterpret_cast<MlpLds *>(smem);
+    char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
+    if (SK == kSkLearned) {
+        stage_weights(mlpw, B.mlp);
+        __syncthreads();
+    }
+    const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)B.lds_state_bytes;
+    char *mine = waves + (size_t)wave * per_wave;
     uint32_t *tree = reinterpret_cast<uint32_t *>(mine);
+    char *mlps = mine + B.lds_tree_bytes;
     char *state;
     if (B.hbm_state) {
         const uint64_t slot = (uint64_t)blockIdx.x * B.waves_per_block + wave;
         state = B.hbm_state + slot * B.hbm_stride;
     } else {
-        state = mine + B.lds_tree_bytes;
+        state = mine + B.lds_tree_bytes + B.lds_mlp_bytes;
     }
     Work work;
     for (;;) {
@@ -1068,8 +1299,8 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
             if (B.item_off[mid] <= (int64_t)q) lo = mid; else hi = mid - 1;
         }
         const TrajArgs &a = B.mats[B.order[lo]];
-        const Traj<SK != kSkNone, DM, WT> T(a, state, tree);
-        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work);
+        const Traj<OwnRC<SK>::value, DM, WT> T(a, state, tree);
+        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work, mlpw, mlps);
     }
     if (lane_id() == 0 && B.work_totals) {
         atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);

@@ -43,3 +43,36 @@ def test_rejects_degree_beyond_u16():
     M = G.from_coo(n, np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]))
     rc, msg = _create(M.n, M.nnz, M.row_ptr, M.col_idx, M.col_ptr, M.row_idx)
     assert rc == N.PE_ENOTSUP
+
+
+def test_learned_and_training_entry_points_reject_bad_arguments():
+    """Argument checks that run before any device work."""
+    L = N.load()
+    P = C.c_void_p
+    out = P()
+    # trainer: NULL output, NULL or non-finite parameters
+    assert L.perm_est_mlp_create(0, None, None) == N.PE_EINVAL
+    assert L.perm_est_mlp_create(0, None, C.byref(out)) == N.PE_EINVAL
+    bad = np.zeros(N.PE_MLP_NPARAM, dtype=np.float32)
+    bad[100] = np.inf
+    assert L.perm_est_mlp_create(0, bad.ctypes.data, C.byref(out)) == N.PE_EINVAL
+    assert not out.value
+    # NULL handles
+    assert L.perm_est_set_model(None, None, 0.05, None) == N.PE_EINVAL
+    assert L.perm_est_mlp_forward(None, None, 1, None, None) == N.PE_EINVAL
+    assert L.perm_est_mlp_get_params(None, None, None) == N.PE_EINVAL
+    loss = C.c_double()
+    assert L.perm_est_mlp_loss_grad(None, None, None, None, None, 0, 1, C.byref(loss), None, None) == N.PE_EINVAL
+    assert L.perm_est_mlp_train(None, None, None, None, None, 1, 1, 1, 1e-3, 0, None, None) == N.PE_EINVAL
+    nr, ng = C.c_int64(), C.c_int64()
+    counts = np.ones(1, dtype=np.int64)
+    assert L.perm_est_record(None, counts.ctypes.data, 0, None, None, None, C.byref(nr), C.byref(ng),
+                             None) == N.PE_EINVAL
+    L.perm_est_mlp_destroy(None)
+
+
+def test_learned_presets():
+    import paper_2608_15390_amd as Pk
+    s = Pk.preset("learned")
+    assert (s.sk_policy, s.dm_policy, s.initial_dm, s.K0) == (4, 0, 1, 100)
+    assert Pk.preset("learned_threshold").dm_policy == 2

@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark of the MI355X sparse-permanent estimator.
+"""Benchmark of the MI355X sparse-permanent estimator: learned proposal
+against the plain scaled method.
+
+Set-up (untimed, reported): the learned proposal's network is trained on the
+GPU from pairs recorded on 512 generated matrices (n = 1000, planted
+permutation plus 5n uniform entries, avg degree 6) with the plain scaled
+method (one local SK repair per step) as the teacher.
 
 One "step" is one pass of the whole hot path over one batch: the persistent
-trajectory kernel over n_traj trajectories of the large sparse workload
-(n = 1e5, planted random permutation plus 7n uniform extra entries, avg
-degree 8) with the plain scaled schedule (shared initial filter, 100 outer
-SK iterations, one local repair per step), followed by the FP64 reduction.
+trajectory kernel over n_traj = 1e5 trajectories of the large sparse
+workload (n = 1e5, planted random permutation plus 7n uniform extra entries,
+avg degree 8) with the learned proposal, followed by the FP64 reduction.
 The metric is effective samples per second, ESS / T with
-ESS = (sum X)^2 / sum X^2 over the batch and T the wall time of the step.
+ESS = (sum X)^2 / sum X^2 over the batch and T the wall time of the step;
+the plain scaled method (one local SK repair per step, no inner filter) runs
+the same trajectory ids once, untimed by the harness but timed here, and the
+ratio of the two is reported, together with the same comparison at
+n = 1e3 and 1e4 (at n = 1e5 both ESS values collapse towards 1, see
+"degenerate").
 
 Prints one JSON line.  `--gpus N` with N > 1 is not supported: this build
 runs on one GPU (see the design notes for how the work would shard).
@@ -28,7 +38,11 @@ sys.path.insert(0, ROOT)
 METRIC = "effective samples/sec at equal relative error, learned vs plain, n=1e5 avg deg 8"
 HBM_PEAK_GBS = 8000.0
 
-KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/csrc/device.hpp"]
+KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/csrc/device.hpp",
+                  "paper_2608_15390_amd/csrc/mlp.hpp"]
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# algorithmic FLOPs of one 16-candidate tile through the network (8 -> 64 -> 64 -> 1)
+FLOP_PER_TILE = 2 * 16 * (8 * 64 + 64 * 64 + 64)
 
 
 def kernel_hash() -> str:
@@ -78,15 +92,58 @@ def load_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
+def timed_run(est, first, n_traj, seed, sched, want=False):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = est.run(first, n_traj, seed, sched, want_logw=want, want_alive=want)
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def summary(r, secs):
+    return {"ess": r["ess"], "ess_per_s": r["ess"] / secs, "seconds": secs, "traj_per_s": r["n_traj"] / secs,
+            "var_logw": r["var_logw"], "p_match": r["p_match"], "rse": r["rse"],
+            "log_estimate": r["log_estimate"], "steps_per_traj": r["n_steps"] / r["n_traj"]}
+
+
+def ladder(params, plain_sched, learned_sched, seed):
+    """The same comparison on smaller matrices of the same family, where the
+    effective sample size does not collapse."""
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+    from paper_2608_15390_amd import learned as LR
+
+    rows = []
+    for n, cnt in ((1000, 100_000), (10_000, 20_000)):
+        M = G.planted_uniform(n, 7 * n, 5)
+        est = P.PermEst(M)
+        est.set_model(params, LR.MIX_ALPHA)
+        row = {"n": n, "n_traj": cnt}
+        for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
+            est.run(0, 64, seed, sch, want_logw=False, want_alive=False)
+            out, secs = timed_run(est, 0, cnt, seed, sch)
+            row[name] = summary(out["result"], secs)
+        row["ratio"] = row["learned"]["ess_per_s"] / row["plain"]["ess_per_s"]
+        rows.append(row)
+        est.close()
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="large", choices=["large", "small"])
-    ap.add_argument("--schedule", default="local_nodm")
+    ap.add_argument("--method", default="learned", choices=["learned", "plain"],
+                    help="method whose step is timed as `value`")
+    ap.add_argument("--plain-schedule", default="local_nodm")
     ap.add_argument("--n-traj", type=int, default=None)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--train-epochs", type=int, default=4)
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain run and the smaller-n ladder")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -115,6 +172,7 @@ def main() -> int:
 
     import paper_2608_15390_amd as P
     from paper_2608_15390_amd import inputs as G
+    from paper_2608_15390_amd import learned as LR
 
     if args.workload == "large":
         M = G.config_large(1)
@@ -124,15 +182,21 @@ def main() -> int:
         M = G.config_small(1)
         n_traj = args.n_traj or 10_000
         wname = "small_n20"
-    sched = P.preset(args.schedule)
-    scaled = sched.K0 > 0 or sched.sk_policy != 0
-    local = sched.sk_policy == 3
-    dev = torch.device("cuda", 0)
+    learned_sched = P.preset("learned")
+    plain_sched = P.preset(args.plain_schedule)
+    sched = learned_sched if args.method == "learned" else plain_sched
+
+    # ---- set-up (untimed): train the proposal network on the GPU
+    print(f"[bench] training the proposal network ({args.train_epochs} epochs)", file=sys.stderr, flush=True)
+    params, tinfo = LR.train_proposal(G.config_train(1), epochs=args.train_epochs, seed=args.seed)
     est = P.PermEst(M, device=0)
-    # untimed set-up: preprocessing (initial filter, outer SK, templates)
+    est.set_model(params, LR.MIX_ALPHA)
+    # preprocessing (initial filter, outer SK, templates) happens on the first run
     est.run(0, 64, args.seed, sched, want_logw=False, want_alive=False)
     torch.cuda.synchronize()
 
+    print(f"[bench] {args.warmup} warmup + {args.steps} timed steps of {args.method} on {wname}",
+          file=sys.stderr, flush=True)
     results = []
     first_logw = None
     for w in range(args.warmup):
@@ -151,9 +215,12 @@ def main() -> int:
     value = ess / (t1 - t0)
     kern_s = sum(r["seconds"] for r in results) / len(results)
     n_leaf = (2 * M.n + 255) // 256 * 256
-    abytes = sum(algorithmic_bytes(r, M.n, n_leaf, scaled, local) for r in results) / len(results)
+    scaled = sched.sk_policy in (1, 2, 3)
+    abytes = sum(algorithmic_bytes(r, M.n, n_leaf, scaled, sched.sk_policy == 3) for r in results) / len(results)
     achieved = abytes / kern_s / 1e9
-    traffic = load_traffic(wname)
+    tiles = sum(r["n_mlp_tiles"] for r in results) / len(results)
+    mfma_tflops = tiles * FLOP_PER_TILE / kern_s / 1e12
+    traffic = load_traffic(f"{wname}_{args.method}")
     r0 = results[0]
 
     line = {
@@ -167,19 +234,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 weights, f32 scaling",
+        "dtype": "f64 weights, f32 scaling, bf16 network",
         "data": "synthetic (seeded generator)",
         "config": {
             "workload": wname, "n": M.n, "nnz": M.nnz, "n_traj": n_traj,
-            "schedule": args.schedule, "method": "plain scaled (no learned proposal)",
+            "method": args.method, "schedule": "learned" if args.method == "learned" else args.plain_schedule,
             "parallelism": "1 GPU",
         },
-        "estimate": {
-            "log_estimate": r0["log_estimate"], "p_match": r0["p_match"], "rel_spread": r0["rel_spread"],
-            "rse": r0["rse"], "ess": r0["ess"], "var_logw": r0["var_logw"],
-            "traj_per_s": n_traj / (ms_per_step / 1e3), "steps_per_traj": r0["n_steps"] / n_traj,
-            "n_local_sk": r0["n_local_sk"],
-        },
+        "estimate": dict(summary(r0, ms_per_step / 1e3), n_local_sk=r0["n_local_sk"],
+                         n_mlp_tiles=r0["n_mlp_tiles"]),
+        "training": dict(tinfo, matrices="512 x (n=1000, avg degree 6)", teacher="local_nodm (local SK repair per step)",
+                         mix_alpha=LR.MIX_ALPHA),
         "roofline": {
             "kernel": "pe::traj_kernel",
             "bound": "hbm",
@@ -190,13 +255,38 @@ def main() -> int:
             "traffic": traffic,
             "algorithmic_bytes_per_launch": abytes,
             "kernel_ms": kern_s * 1e3,
+            "mfma_bf16_tflops": mfma_tflops,
+            "mfma_frac": mfma_tflops / MFMA_BF16_PEAK_TFLOPS,
         },
     }
 
+    if not args.no_compare and args.workload == "large":
+        other = plain_sched if args.method == "learned" else learned_sched
+        oname = "plain" if args.method == "learned" else "learned"
+        print(f"[bench] comparison run: {oname}, same trajectory ids", file=sys.stderr, flush=True)
+        est.run(0, 64, args.seed, other, want_logw=False, want_alive=False)
+        out, secs = timed_run(est, 0, n_traj, args.seed, other)
+        mine = summary(r0, ms_per_step / 1e3)
+        theirs = summary(out["result"], secs)
+        learned_s, plain_s = (mine, theirs) if args.method == "learned" else (theirs, mine)
+        print("[bench] ladder n=1e3, 1e4", file=sys.stderr, flush=True)
+        lad = ladder(params, plain_sched, learned_sched, args.seed)
+        line["compare"] = {
+            "plain_schedule": args.plain_schedule,
+            "learned": learned_s, "plain": plain_s,
+            "ratio_learned_over_plain": learned_s["ess_per_s"] / plain_s["ess_per_s"],
+            "degenerate": bool(learned_s["ess"] < 10 and plain_s["ess"] < 10),
+            "ladder": lad,
+        }
+
     if not args.no_cpu_baseline:
+        from oracle import mlp as R
         from oracle import oracle as O
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         A = O.OMatrix(M)
-        osched = O.preset(args.schedule)
+        osched = O.preset("learned" if args.method == "learned" else args.plain_schedule)
+        if args.method == "learned":
+            osched = osched.replace(model=R.quantize(params.cpu().numpy().astype(np.float64)), mix_alpha=LR.MIX_ALPHA)
         pre = O.prep(A, osched)
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         # bounded sample: first ids of the timed batch, grown until ~cpu_seconds

@@ -116,6 +116,8 @@ typedef struct {
     int64_t n_decrements;      /* residual-degree decrements                */
     int64_t n_local_entries;   /* entries gathered or summed by local repair */
     int64_t n_local_values;    /* scaling values recomputed by local repair */
+    int64_t n_mlp_tiles;       /* 16-candidate tiles through the learned
+                                  proposal's network                        */
 } perm_est_result;
 
 /* Create a handle for one n x n matrix A given in both CSR and CSC form

@@ -341,12 +341,15 @@ def learned_logit(model: np.ndarray, x) -> int:
     return int(L.or_learned_logit(m.ctypes.data, xx.ctypes.data))
 
 
-def learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row) -> np.ndarray:
+def learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row, s_u, c2_u) -> np.ndarray:
+    """Features of a candidate edge; s_u = sum of floor(2^20 / deg w) over
+    the candidate's residual neighbours w, c2_u = how many of them other
+    than v have degree <= 2."""
     L = lib()
     L.or_learned_features.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32,
-                                      C.c_int32, C.c_int32, C.c_void_p]
+                                      C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_void_p]
     x = np.zeros(MLP_IN, dtype=np.float64)
-    L.or_learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row, x.ctypes.data)
+    L.or_learned_features(deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_is_row, s_u, c2_u, x.ctypes.data)
     return x
 
 

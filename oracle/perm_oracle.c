@@ -485,7 +485,13 @@ int or_prep(const or_mat *A, int32_t initial_dm, int32_t K0, int32_t prec,
  *   end) at step t:
  *     x0 = min(deg rho, 255)/64, x1 = min(deg gam, 255)/64,
  *     x2 = Q(plog2(r0[rho])/4), x3 = Q(plog2(c0[gam])/4), x4 = Q(t/n),
- *     x5 = 1 if the selected vertex is a row, x6 = x7 = 0;
+ *     x5 = 1 if the selected vertex is a row,
+ *     x6 = Q(plog2(S_u / 2^20)/4) with S_u = sum over the residual
+ *          neighbours w of the candidate u (v included) of
+ *          floor(2^20 / deg w): one half-step of SK from unit scaling,
+ *          in exact integer arithmetic,
+ *     x7 = min(#{w in N(u), w != v, deg w <= 2}, 255)/64 (neighbours of u
+ *          the step leaves with at most one option);
  *   Q(y) = clamp(rint(64 y), -256, 255)/64; plog2(s) = e - 2 + 2m for
  *   s = m 2^e, m in [0.5, 1) (piecewise-linear log2, exact);
  *   h1 = A(x W1 + b1), h2 = A(h1 W2 + b2), L = Lq(h2 . w3 + b3) with
@@ -516,7 +522,7 @@ double or_plog2(double s)
 }
 
 void or_learned_features(int32_t deg_rho, int32_t deg_gam, double r0_rho, double c0_gam,
-                         int32_t t, int32_t n, int32_t v_is_row, double *x)
+                         int32_t t, int32_t n, int32_t v_is_row, int64_t s_u, int32_t c2_u, double *x)
 {
     x[0] = (double)(deg_rho < 255 ? deg_rho : 255) / 64.0;
     x[1] = (double)(deg_gam < 255 ? deg_gam : 255) / 64.0;
@@ -524,8 +530,8 @@ void or_learned_features(int32_t deg_rho, int32_t deg_gam, double r0_rho, double
     x[3] = q64(or_plog2(c0_gam) / 4.0, -256.0, 255.0);
     x[4] = q64((double)t / (double)n, -256.0, 255.0);
     x[5] = v_is_row ? 1.0 : 0.0;
-    x[6] = 0.0;
-    x[7] = 0.0;
+    x[6] = q64(or_plog2((double)s_u / 1048576.0) / 4.0, -256.0, 255.0);
+    x[7] = (double)(c2_u < 255 ? c2_u : 255) / 64.0;
 }
 
 /* logit in units of 1/16 (exact grid arithmetic) */
@@ -719,6 +725,27 @@ static int32_t residual_neighbours(const or_mat *A, const traj_work *w, int32_t 
     return k;
 }
 
+/* S_u and the degree-<=2 count of features x6 / x7 of the learned proposal */
+static void candidate_stats(const or_mat *A, const traj_work *w, int32_t u, int32_t v, int64_t *s_u,
+                            int32_t *c2_u)
+{
+    int32_t n = A->n;
+    int64_t S = 0;
+    int32_t c2 = 0;
+    int32_t beg, end;
+    if (u < n) { beg = A->row_ptr[u]; end = A->row_ptr[u + 1]; }
+    else { beg = A->col_ptr[u - n]; end = A->col_ptr[u - n + 1]; }
+    for (int32_t p = beg; p < end; ++p) {
+        int32_t y = u < n ? n + A->col_idx[p] : A->row_idx[p];
+        int32_t e = u < n ? p : A->csc2csr[p];
+        if (!w->act[y] || w->removed[e] || w->deg[y] <= 0) continue;
+        S += 1048576 / w->deg[y];
+        if (y != v && w->deg[y] <= 2) ++c2;
+    }
+    *s_u = S;
+    *c2_u = c2;
+}
+
 static void recount_degrees(const or_mat *A, traj_work *w)
 {
     for (int32_t x = 0; x < 2 * A->n; ++x)
@@ -900,7 +927,11 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
                 int32_t y = w->cand_v[a];
                 int32_t rho = v_is_row ? v : y, gam = v_is_row ? y : v;
                 double x[MLP_IN];
-                or_learned_features(w->deg[rho], w->deg[gam], r0[rho], c0[gam - n], t, n, v_is_row, x);
+                int64_t s_u;
+                int32_t c2_u;
+                candidate_stats(A, w, y, v, &s_u, &c2_u);
+                or_learned_features(w->deg[rho], w->deg[gam], r0[rho], c0[gam - n], t, n, v_is_row, s_u, c2_u,
+                                    x);
                 Lg[a] = or_learned_logit(S->model, x);
             }
             or_learned_weights(Lg, kc, S->mix_alpha, w->cand_w);

@@ -55,6 +55,7 @@ class Result(C.Structure):
         ("n_decrements", C.c_int64),
         ("n_local_entries", C.c_int64),
         ("n_local_values", C.c_int64),
+        ("n_mlp_tiles", C.c_int64),
     ]
 
     def as_dict(self):

@@ -109,6 +109,8 @@ struct Tune {
 
 }  // namespace
 
+constexpr int kWorkTotals = 6;  // launch-wide work counters, see BatchArgs::work_totals
+
 struct perm_est {
     int device = 0;
     uint32_t opt_flags = 0;
@@ -474,7 +476,7 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
     int rc;
-    if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, 5)) || (rc = dalloc(&h->flags, 8)) ||
+    if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, kWorkTotals)) || (rc = dalloc(&h->flags, 8)) ||
         (rc = dalloc(&h->batch_dev, 1)) || (rc = dalloc(&h->rec_ctr, 2)))
         return rc;
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
@@ -688,7 +690,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipMemcpyAsync(h->batch_dev, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
     k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
     k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
-    k_fill_i32<<<1, 64, 0, s>>>(10, reinterpret_cast<int32_t *>(h->work_totals), 0);
+    k_fill_i32<<<1, 64, 0, s>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
     if (rec) k_fill_i32<<<1, 64, 0, s>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
     PE_HIP(hipEventRecord(h->ev0, s));
     launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, s, h->batch_dev);
@@ -704,7 +706,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipEventRecord(h->ev1, s));
     std::vector<DevStats> st(count);
     uint32_t err_bits = 0;
-    unsigned long long wt_tot[5];
+    unsigned long long wt_tot[kWorkTotals];
     if (res) PE_HIP(hipMemcpyAsync(st.data(), h->stats, sizeof(DevStats) * count, hipMemcpyDeviceToHost, s));
     PE_HIP(hipMemcpyAsync(wt_tot, h->work_totals, sizeof(wt_tot), hipMemcpyDeviceToHost, s));
     PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
@@ -737,6 +739,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
             r.n_decrements = (int64_t)wt_tot[1];
             r.n_local_entries = (int64_t)wt_tot[2];
             r.n_local_values = (int64_t)wt_tot[3];
+            r.n_mlp_tiles = (int64_t)wt_tot[5];
         }
     }
     return PE_OK;

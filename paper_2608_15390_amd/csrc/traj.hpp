@@ -455,6 +455,7 @@ struct Work {
     uint64_t loc_entries = 0; // entries gathered or summed by local repairs
     uint64_t loc_values = 0;  // scaling values recomputed by local repairs
     uint64_t sweeps = 0;      // full SK iterations
+    uint64_t mlp_tiles = 0;   // 16-candidate tiles through the proposal network
 };
 
 __device__ __forceinline__ uint64_t lemire_from(uint64_t x, uint64_t W, uint64_t seed, uint32_t k,
@@ -683,7 +684,8 @@ struct OwnRC { static constexpr bool value = SK == kSkFixed || SK == kSkAdaptive
 // features of the candidate edge of Eq. (q) for the learned proposal (see
 // the definition in the oracle): exact operations only
 __device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uint32_t deg_gam, float r0_rho,
-                                                 float c0_gam, int32_t t, int32_t n, bool v_row) {
+                                                 float c0_gam, int32_t t, int32_t n, bool v_row, uint64_t s_u,
+                                                 int32_t c2_u) {
     auto q64 = [](double y) -> float {
         double k = rint(y * 64.0);
         k = k < -256.0 ? -256.0 : (k > 255.0 ? 255.0 : k);
@@ -700,8 +702,63 @@ __device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uin
     x[3] = q64(plog2((double)c0_gam) / 4.0);
     x[4] = q64((double)t / (double)n);
     x[5] = v_row ? 1.0f : 0.0f;
-    x[6] = 0.0f;
-    x[7] = 0.0f;
+    x[6] = q64(plog2((double)s_u * (1.0 / 1048576.0)) / 4.0);
+    x[7] = (float)(c2_u < 255 ? c2_u : 255) / 64.0f;
+}
+
+// Neighbourhood statistics of the candidate u held by each lane (cand):
+// s_u = sum over the residual neighbours w of u of floor(2^20 / deg w) and
+// c2_u = #{w != v : deg w <= 2}.  The candidates' lists are flattened over
+// the wave (64 entries per pass) and summed per owner with a segmented scan;
+// integer sums, so the result does not depend on the order.
+template <class TT>
+__device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t v, uint64_t &s_u, int32_t &c2_u) {
+    const int l = lane_id();
+    const bool u_row = u < T.n;
+    int32_t ub = 0, ue = 0;
+    if (cand) T.list(u, ub, ue);
+    int32_t total;
+    const int32_t off = wave_excl_scan_i32(cand ? ue - ub : 0, total);
+    const int32_t len = cand ? ue - ub : 0;
+    s_u = 0;
+    c2_u = 0;
+    for (int32_t base = 0; base < total; base += kWave) {
+        const int32_t f = base + l;
+        const bool valid = f < total;
+        const int own = owner_lane(valid ? f : total - 1, off);
+        const int32_t o_off = __shfl(off, own);
+        const int32_t o_ub = __shfl(ub, own);
+        const bool o_row = __shfl((int)u_row, own) != 0;
+        uint32_t sv = 0;
+        int32_t cv = 0;
+        if (valid) {
+            int32_t w, e;
+            float bv;
+            T.entry(o_row, o_ub + (f - o_off), w, e, bv);
+            const uint32_t dw = T.deg[w];
+            if (dw != kRetired && dw != 0 && !T.removed(e)) {
+                sv = (1u << 20) / dw;
+                cv = (w != v && dw <= 2u) ? 1 : 0;
+            }
+        }
+        // inclusive scan within runs of equal owner (runs are contiguous)
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t ys = __shfl_up(sv, o);
+            const int32_t yc = __shfl_up(cv, o);
+            const int yo = __shfl_up(own, o);
+            if (l >= o && yo == own) { sv += ys; cv += yc; }
+        }
+        // each candidate lane takes the scan value at the last lane of its run
+        const int32_t lo_f = off > base ? off : base;
+        int32_t hi_f = off + len;
+        const int32_t cap = base + kWave < total ? base + kWave : total;
+        hi_f = hi_f < cap ? hi_f : cap;
+        const int src = hi_f > lo_f ? hi_f - 1 - base : 0;
+        const uint32_t seg_s = __shfl(sv, src);
+        const int32_t seg_c = __shfl(cv, src);
+        if (hi_f > lo_f) { s_u += seg_s; c2_u += seg_c; }
+    }
 }
 
 // Logits (units of 1/16) of the candidates held by the lanes of one list
@@ -709,13 +766,13 @@ __device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uin
 // 16-lane tiles.  Lanes without a candidate return 0.
 __device__ int32_t learned_logits(const MlpLds *W, char *scratch, bool cand, uint32_t deg_rho,
                                   uint32_t deg_gam, float r0_rho, float c0_gam, int32_t t, int32_t n,
-                                  bool v_row, int32_t chunk_len) {
+                                  bool v_row, uint64_t s_u, int32_t c2_u, int32_t chunk_len) {
     const int l = lane_id();
     float *feat = reinterpret_cast<float *>(scratch);                    // [64][8]
     int32_t *logit = reinterpret_cast<int32_t *>(scratch + 64 * 8 * 4);  // [64]
     TileLds *tile = reinterpret_cast<TileLds *>(scratch + 64 * 8 * 4 + 64 * 4);
     float x[8];
-    learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_row);
+    learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_row, s_u, c2_u);
 #pragma unroll
     for (int k = 0; k < 8; ++k) feat[l * 8 + k] = cand ? x[k] : 0.0f;
     wave_fence();
@@ -834,8 +891,12 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 if (kc > 1) {
                     const float r0r = a.r0 ? a.r0[cand ? rho_c : 0] : 1.0f;
                     const float c0g = a.c0 ? a.c0[cand ? gam_c - n : 0] : 1.0f;
+                    uint64_t su;
+                    int32_t c2;
+                    candidate_stats(T, cand, cy, v, su, c2);
                     L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
-                                       t, n, v_row, ve - vb);
+                                       t, n, v_row, su, c2, ve - vb);
+                    work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
                 }
                 int32_t lmx = cand ? L : -2147483647;
 #pragma unroll
@@ -874,6 +935,9 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 // records are contiguous.
                 if (a.rec_x && kc >= 2 && (t % a.rec_stride) == 0) {
                     const float ssum = wave_sum_f32(cand ? s : 0.0f);
+                    uint64_t su;
+                    int32_t c2;
+                    candidate_stats(T, cand, cy, v, su, c2);
                     unsigned long long old = 0;
                     if (l == 0) {
                         const unsigned long long cur = __hip_atomic_load(a.rec_counter, __ATOMIC_RELAXED,
@@ -894,7 +958,8 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                             const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
                             float x[8];
                             learned_features(x, v_row ? deg_v : cd, v_row ? cd : deg_v,
-                                             a.r0 ? a.r0[rho_c] : 1.0f, a.c0 ? a.c0[gam_c - n] : 1.0f, t, n, v_row);
+                                             a.r0 ? a.r0[rho_c] : 1.0f, a.c0 ? a.c0[gam_c - n] : 1.0f, t, n, v_row,
+                                             su, c2);
                             float4 *xo = reinterpret_cast<float4 *>(a.rec_x + r * 8);
                             xo[0] = make_float4(x[0], x[1], x[2], x[3]);
                             xo[1] = make_float4(x[4], x[5], x[6], x[7]);
@@ -965,9 +1030,13 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                     const int32_t rho_c = v_row ? v : y, gam_c = v_row ? y : v;
                     const float r0r = a.r0 ? a.r0[c0 ? rho_c : 0] : 1.0f;
                     const float c0g = a.c0 ? a.c0[c0 ? gam_c - n : 0] : 1.0f;
+                    uint64_t su;
+                    int32_t c2;
+                    candidate_stats(T, c0, y, v, su, c2);
                     const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
-                                                     v_row ? dy : (uint32_t)kc, r0r, c0g, t, n, v_row,
+                                                     v_row ? dy : (uint32_t)kc, r0r, c0g, t, n, v_row, su, c2,
                                                      min(kWave, ve - base));
+                    work.mlp_tiles += (uint64_t)((min(kWave, ve - base) + 15) / 16);
                     const uint64_t msk = ballot(c0);
                     if (c0) { T.lst_b[idx0 + rank_below(msk)] = L; lmx = L > lmx ? L : lmx; }
                     idx0 += __popcll(msk);
@@ -1247,7 +1316,7 @@ struct BatchArgs {
     int32_t count;
     int64_t total;
     uint32_t *work_next;      // item counter (zeroed before launch)
-    unsigned long long *work_totals;  // [5], see TrajArgs
+    unsigned long long *work_totals;  // [6]: scanned, decrements, local entries, local values, sweeps, tiles
     char *hbm_state;          // HBM tier: base of per-wave slots; nullptr = LDS tier
     uint64_t hbm_stride;
     int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
@@ -1308,6 +1377,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
         atomicAdd(B.work_totals + 2, (unsigned long long)work.loc_entries);
         atomicAdd(B.work_totals + 3, (unsigned long long)work.loc_values);
         atomicAdd(B.work_totals + 4, (unsigned long long)work.sweeps);
+        atomicAdd(B.work_totals + 5, (unsigned long long)work.mlp_tiles);
     }
 }
 

@@ -54,3 +54,24 @@ def dense_values(M) -> np.ndarray:
     rows = np.repeat(np.arange(n), np.diff(M.row_ptr))
     D[rows, M.col_idx] = 1.0 if M.val is None else M.val.astype(np.float64)
     return D
+
+
+def stats_by_hand(M, o, u, v):
+    """S_u and the degree-<=2 count from the oracle's state snapshot, written
+    out independently of the oracle."""
+    n = M.n
+    act, deg, removed = o["act"].astype(bool), o["deg"], o["removed"].astype(bool)
+    if u < n:
+        lo, hi = M.row_ptr[u], M.row_ptr[u + 1]
+        nb, edges = M.col_idx[lo:hi] + n, np.arange(lo, hi)
+    else:
+        lo, hi = M.col_ptr[u - n], M.col_ptr[u - n + 1]
+        nb = M.row_idx[lo:hi]
+        edges = np.array([M.row_ptr[i] + np.searchsorted(M.col_idx[M.row_ptr[i]:M.row_ptr[i + 1]], u - n)
+                          for i in nb], dtype=np.int64)
+    S, c2 = 0, 0
+    for w, e in zip(nb, edges):
+        if act[w] and not removed[e]:
+            S += (1 << 20) // int(deg[w])
+            c2 += int(w != v and deg[w] <= 2)
+    return S, c2

@@ -21,6 +21,7 @@ import pytest
 from oracle import mlp as R
 from oracle import oracle as O
 from paper_2608_15390_amd import inputs as G
+from oracle_tools import stats_by_hand
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -270,7 +271,8 @@ def test_recorded_pairs_match_the_oracle():
         # features of every candidate edge, from the oracle's definition
         for i, u in enumerate(cand):
             rho, gam = (v, int(u)) if v_row else (int(u), v)
+            S, c2 = stats_by_hand(M, o, int(u), v)
             fr = O.learned_features(int(o["deg"][rho]), int(o["deg"][gam]), float(pre.r[rho]),
-                                    float(pre.c[gam - n]), t, n, int(v_row))
+                                    float(pre.c[gam - n]), t, n, int(v_row), S, c2)
             np.testing.assert_array_equal(x[sl][i], np.asarray(fr, dtype=np.float32), err_msg=str((b, k, t, i)))
     bt.close()

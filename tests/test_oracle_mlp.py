@@ -9,7 +9,7 @@ import pytest
 from oracle import mlp as R
 from oracle import oracle as O
 from paper_2608_15390_amd import inputs as G
-from oracle_tools import dense_values, enumerate_tree
+from oracle_tools import dense_values, enumerate_tree, stats_by_hand
 
 
 def _data(seed, groups=12):
@@ -87,12 +87,58 @@ def test_grid_network_is_exact_in_float32_in_any_order():
     model = R.quantize(R.init(9, scale=1.5))
     for trial in range(8):
         x = O.learned_features(int(g.integers(0, 40)), int(g.integers(0, 40)), float(g.uniform(0.01, 3)),
-                               float(g.uniform(0.01, 3)), int(g.integers(0, 100)), 100, trial % 2)
+                               float(g.uniform(0.01, 3)), int(g.integers(0, 100)), 100, trial % 2,
+                               int(g.integers(1 << 15, 1 << 26)), int(g.integers(0, 300)))
         ref = O.learned_logit(model, x)
         for _ in range(3):
             order8 = [int(i) for i in g.permutation(8)]
             order64 = [int(i) for i in g.permutation(64)]
             assert _float32_logit(model, x, order8, order64) == ref
+
+
+def test_candidate_features_by_hand():
+    # S_u = 1.5 * 2^20: plog2(1.5) = 0.5, x6 = Q(0.125) = 8/64
+    x = O.learned_features(3, 2, 1.0, 1.0, 5, 10, 1, 3 << 19, 2)
+    assert x[6] == 0.125 and x[7] == 2 / 64
+    # degrees and counts clamp at 255, t/n on the 1/64 grid, r0 = 2 -> plog2 = 1
+    x = O.learned_features(300, 7, 2.0, 0.5, 1, 3, 0, 1 << 20, 1000)
+    assert x[0] == 255 / 64 and x[1] == 7 / 64 and x[7] == 255 / 64
+    assert x[2] == 0.25 and x[3] == -0.25 and x[4] == 21 / 64 and x[5] == 0.0 and x[6] == 0.0
+
+
+@pytest.mark.parametrize("name", ["learned", "learned_threshold"])
+def test_learned_proposal_at_a_step_from_its_definition(name):
+    """At a stopped step the oracle's learned proposal equals the one
+    rebuilt here from the state snapshot: features (with S_u and the
+    degree-<=2 count computed by hand), grid logits, integer weights."""
+    model = R.quantize(R.init(21, scale=2.0))
+    sched = O.preset(name).replace(model=model, mix_alpha=0.1)
+    g = np.random.default_rng(3)
+    checked = 0
+    for trial in range(12):
+        M = G.planted_bernoulli(40, 0.12, int(g.integers(1 << 30)), planted="random")
+        A = O.OMatrix(M)
+        pre = O.prep(A, sched)
+        n = M.n
+        t = int(g.integers(0, 30))
+        o = O.probe(A, sched, pre, seed=5, k=trial, forced=[], stop_at=t)
+        if o["stopped"] != 1 or len(o["cand"]) < 2:
+            continue
+        act = o["act"].astype(bool)
+        v = int(np.argmin(np.where(act, o["deg"], 1 << 30)))
+        v_row = v < n
+        L = []
+        for u in o["cand"]:
+            u = int(u)
+            rho, gam = (v, u) if v_row else (u, v)
+            S, c2 = stats_by_hand(M, o, u, v)
+            x = O.learned_features(int(o["deg"][rho]), int(o["deg"][gam]), float(pre.r[rho]),
+                                   float(pre.c[gam - n]), t, n, int(v_row), S, c2)
+            L.append(O.learned_logit(model, x))
+        w = O.learned_weights(L, 0.1).astype(np.float64)
+        np.testing.assert_array_equal(o["prob"], w / w.sum())
+        checked += 1
+    assert checked >= 6
 
 
 def test_learned_weights_properties():

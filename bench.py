@@ -102,6 +102,44 @@ def timed_run(est, first, n_traj, seed, sched, want=False):
     return out, time.perf_counter() - t0
 
 
+def chunked_run(est, first, n_traj, seed, sched, chunk):
+    """n_traj trajectories as consecutive launches of at most `chunk` ids
+    (results are identical per id), printing progress between launches.
+    The batch statistics are recomputed from the per-trajectory ln X in FP64
+    on the host: S1 = sum X, S2 = sum X^2 by log-sum-exp, ESS = S1^2 / S2."""
+    import numpy as np
+    import torch
+
+    lws, als, secs, done, steps = [], [], 0.0, 0, 0
+    while done < n_traj:
+        c = min(chunk, n_traj - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = est.run(first + done, c, seed, sched, want_logw=True, want_alive=True)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        lws.append(out["logw"].cpu().numpy())
+        als.append(out["alive"].cpu().numpy())
+        steps += out["result"]["n_steps"]
+        done += c
+        print(f"[bench]   {done}/{n_traj} trajectories, {secs:.1f} s", file=sys.stderr, flush=True)
+    lw = np.concatenate(lws)
+    al = np.concatenate(als).astype(bool)
+    r = {"n_traj": n_traj, "n_alive": int(al.sum()), "p_match": float(al.mean()), "n_steps": steps,
+         "ess": 0.0, "var_logw": float("nan"), "rse": float("nan"), "log_estimate": float("-inf")}
+    if al.any():
+        x = lw[al]
+        m = x.max()
+        ls1 = m + math.log(np.exp(x - m).sum())
+        ls2 = 2 * m + math.log(np.exp(2 * (x - m)).sum())
+        r["log_estimate"] = ls1 - math.log(n_traj)
+        r["ess"] = math.exp(2 * ls1 - ls2)
+        rel_var = max(0.0, math.exp(ls2 - 2 * ls1) * n_traj - 1.0) * n_traj / max(n_traj - 1, 1)
+        r["rse"] = math.sqrt(rel_var / n_traj)
+        r["var_logw"] = float(np.var(x, ddof=1)) if x.size > 1 else 0.0
+    return r, secs
+
+
 def summary(r, secs):
     return {"ess": r["ess"], "ess_per_s": r["ess"] / secs, "seconds": secs, "traj_per_s": r["n_traj"] / secs,
             "var_logw": r["var_logw"], "p_match": r["p_match"], "rse": r["rse"],
@@ -265,9 +303,9 @@ def main() -> int:
         oname = "plain" if args.method == "learned" else "learned"
         print(f"[bench] comparison run: {oname}, same trajectory ids", file=sys.stderr, flush=True)
         est.run(0, 64, args.seed, other, want_logw=False, want_alive=False)
-        out, secs = timed_run(est, 0, n_traj, args.seed, other)
+        res_o, secs = chunked_run(est, 0, n_traj, args.seed, other, max(1, n_traj // 4))
         mine = summary(r0, ms_per_step / 1e3)
-        theirs = summary(out["result"], secs)
+        theirs = summary(res_o, secs)
         learned_s, plain_s = (mine, theirs) if args.method == "learned" else (theirs, mine)
         print("[bench] ladder n=1e3, 1e4", file=sys.stderr, flush=True)
         lad = ladder(params, plain_sched, learned_sched, args.seed)

@@ -25,6 +25,9 @@ FLAGS = [
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: the learned trajectory kernel
+    # then fits 4 waves per SIMD (AGPRs would round it past 128 registers)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall",
     "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),

@@ -20,13 +20,42 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
+// Lane src's value in every lane (src must be the same in all lanes); the
+// result is wave-uniform, so the compiler may keep it in a scalar register.
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int src) {
+    if constexpr (sizeof(T) == 8) {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+        u = ((uint64_t)hi << 32) | lo;
+        T r;
+        __builtin_memcpy(&r, &u, 8);
+        return r;
+    } else if constexpr (sizeof(T) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &v, 4);
+        u = (uint32_t)__builtin_amdgcn_readlane((int)u, src);
+        T r;
+        __builtin_memcpy(&r, &u, 4);
+        return r;
+    } else {
+        return (T)__builtin_amdgcn_readlane((int)v, src);
+    }
+}
+
+// a value that every lane already holds, made visibly uniform
+template <typename T>
+__device__ __forceinline__ T uniform(T v) { return read_lane(v, 0); }
+
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         uint32_t y = __shfl_xor(x, o);
         x = y < x ? y : x;
     }
-    return x;
+    return uniform(x);
 }
 
 __device__ __forceinline__ float wave_max_f32(float x) {
@@ -36,25 +65,25 @@ __device__ __forceinline__ float wave_max_f32(float x) {
         float y = __shfl_xor(x, o);
         x = (y > x) ? y : x;
     }
-    return x;
+    return uniform(x);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    return uniform(x);
 }
 
 __device__ __forceinline__ float wave_sum_f32(float x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    return uniform(x);
 }
 
 __device__ __forceinline__ int wave_sum_i32(int x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    return uniform(x);
 }
 
 // inclusive prefix sum over the 64 lanes in lane order
@@ -75,8 +104,6 @@ __device__ __forceinline__ int rank_below(uint64_t mask) {
     return __popcll(below);
 }
 
-template <typename T>
-__device__ __forceinline__ T read_lane(T v, int src) { return __shfl(v, src); }
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two

@@ -37,21 +37,34 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// Weights in matrix-core form, staged once per block in LDS:
-//   w1[16][64] bf16 (rows 8..15 zero), w2[64][64] bf16, and float b1, b2, w3, b3.
+// Weights in matrix-core form, staged once per block in LDS, each lane's
+// four B-operand values contiguous (one 8-byte LDS read per MFMA):
+//   w1[nt][lane < 32][4] = W1[4 (lane / 16) + j][16 nt + lane % 16] (the K = 16
+//     tile's rows 8..15 are zero and not stored),
+//   w2[ks][nt][lane][4] = W2[16 ks + 4 (lane / 16) + j][16 nt + lane % 16],
+// and float b1, b2, w3, b3.
 struct MlpLds {
-    short w1[16 * kH];
+    short w1[kIn * kH];
     short w2[kH * kH];
     float b1[kH], b2[kH], w3[kH];
     float b3;
 };
 
+// position of W2[r][c] in MlpLds::w2
+__device__ __forceinline__ int w2_index(int r, int c) {
+    const int ks = r >> 4, nt = c >> 4, lane = 16 * ((r & 15) >> 2) + (c & 15);
+    return ((ks * 4 + nt) * 64 + lane) * 4 + (r & 3);
+}
+
 __device__ void stage_weights(MlpLds *s, const float *P) {
-    for (int i = threadIdx.x; i < 16 * kH; i += blockDim.x) {
-        const int k = i / kH, c = i % kH;
-        s->w1[i] = k < kIn ? to_bf16(P[kOffW1 + k * kH + c]) : (short)0;
+    for (int i = threadIdx.x; i < kIn * kH; i += blockDim.x) {
+        const int j = i & 3, lane = (i >> 2) & 31, nt = i >> 7;
+        s->w1[i] = to_bf16(P[kOffW1 + (4 * (lane >> 4) + j) * kH + 16 * nt + (lane & 15)]);
     }
-    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) s->w2[i] = to_bf16(P[kOffW2 + i]);
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
+        const int r = i >> 6, c = i & 63;
+        s->w2[w2_index(r, c)] = to_bf16(P[kOffW2 + i]);
+    }
     for (int i = threadIdx.x; i < kH; i += blockDim.x) {
         s->b1[i] = P[kOffB1 + i];
         s->b2[i] = P[kOffB2 + i];
@@ -88,9 +101,8 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
     // layer 1: [16 x 16] x [16 x 64]
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        bf16x4 b;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = W->w1[(r0 + j) * kH + 16 * nt + c0];
+        bf16x4 b = {0, 0, 0, 0};
+        if (l < 32) b = *reinterpret_cast<const bf16x4 *>(&W->w1[(nt * 32 + l) * 4]);
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         acc = mfma16(xa, b, acc);
 #pragma unroll
@@ -112,9 +124,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            bf16x4 b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = W->w2[(16 * ks + r0 + j) * kH + 16 * nt + c0];
+            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&W->w2[((ks * 4 + nt) * 64 + l) * 4]);
             acc = mfma16(a2[ks], b, acc);
         }
 #pragma unroll
@@ -275,7 +285,7 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const floa
             for (int cs = 0; cs < 4; ++cs) {
                 bf16x4 b;  // B[c][k] = W2[k][c], k = 16 nt + c0, c = 16 cs + q0 + j
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = W.w2[(16 * nt + c0) * kH + 16 * cs + q0 + j];
+                for (int j = 0; j < 4; ++j) b[j] = W.w2[w2_index(16 * nt + c0, 16 * cs + q0 + j)];
                 acc = mfma16(dza[cs], b, acc);
             }
 #pragma unroll

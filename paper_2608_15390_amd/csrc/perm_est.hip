@@ -408,6 +408,28 @@ void launch_traj(int sk, bool dm, bool wt, unsigned blocks, unsigned threads, si
     }
 }
 
+template <int SK>
+const void *kernel_dm(bool dm, bool wt) {
+    if (dm) return wt ? (const void *)&traj_kernel<SK, true, true> : (const void *)&traj_kernel<SK, true, false>;
+    return wt ? (const void *)&traj_kernel<SK, false, true> : (const void *)&traj_kernel<SK, false, false>;
+}
+
+// the trajectory kernel instance a launch uses (for occupancy queries)
+const void *traj_kernel_fn(int sk, bool dm, bool wt) {
+    switch (sk) {
+        case PE_SK_NONE: return kernel_dm<kSkNone>(dm, wt);
+        case PE_SK_FIXED: return kernel_dm<kSkFixed>(dm, wt);
+        case PE_SK_ADAPTIVE: return kernel_dm<kSkAdaptive>(dm, wt);
+        case PE_SK_LOCAL: return kernel_dm<kSkLocal>(dm, wt);
+        default: return kernel_dm<kSkLearned>(dm, wt);
+    }
+}
+
+// upper bound on resident trajectory waves per CU for the default launch shape
+#ifndef PE_MAX_WAVES_PER_CU
+#define PE_MAX_WAVES_PER_CU 32
+#endif
+
 int check_schedule(const perm_est_schedule *s) {
     if (!s) return fail(PE_EINVAL, "schedule is NULL");
     if (s->vertex_rule < 0 || s->vertex_rule > 1) return fail(PE_EINVAL, "bad vertex_rule");
@@ -661,7 +683,19 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
     const size_t shmem = block_fixed + (size_t)wpb * per_wave;
     if (shmem > kLdsBlock) return fail(PE_ENOTSUP, "per-trajectory LDS need exceeds one block's LDS");
-    size_t per_cu = per_cu_req > 0 ? (size_t)per_cu_req : std::max<size_t>(1, 16 / wpb);
+    size_t per_cu;
+    if (per_cu_req > 0) {
+        per_cu = (size_t)per_cu_req;
+    } else {
+        // as many resident blocks as registers and LDS allow, up to the cap
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, traj_kernel_fn(sched->sk_policy, dm, wt), wpb * kWave,
+                                                         shmem) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = std::max(1, 16 / wpb);
+        }
+        per_cu = (size_t)std::max(1, std::min(nb, PE_MAX_WAVES_PER_CU / wpb));
+    }
     per_cu = std::max<size_t>(1, std::min<size_t>(per_cu, kLdsCU / std::max<size_t>(shmem, 1)));
     const unsigned blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((total + wpb - 1) / wpb, (int64_t)h->cu_count * (int64_t)per_cu));

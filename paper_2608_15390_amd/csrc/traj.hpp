@@ -219,8 +219,10 @@ struct Traj {
 
     // Minimum-degree selection; also hands back the leaf group of the
     // selected vertex and this lane's four leaves of it, so the group
-    // minimum can be refreshed from registers after the step.
-    __device__ bool select_min(int32_t &vsel, int32_t &gsel, uint2 &leaves) const {
+    // minimum can be refreshed from registers after the step, and the
+    // selected vertex's list bounds, loaded for the whole group together
+    // with its leaves (one memory round trip instead of two).
+    __device__ bool select_min(int32_t &vsel, int32_t &gsel, uint2 &leaves, int32_t &vb, int32_t &ve) const {
         const int l = lane_id();
         const int top = a.tree.levels - 1;
         uint32_t v = l < a.tree.size[top] ? level(top)[l] : 0xFFFFFFFFu;
@@ -235,14 +237,28 @@ struct Traj {
         }
         if (!hit) return false;
         leaves = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
+        int32_t lb[4], le[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t x = 256 * g + 4 * l + i;
+            lb[i] = 0;
+            le[i] = 0;
+            if (x < n) { lb[i] = a.A.row_ptr[x]; le[i] = a.A.row_ptr[x + 1]; }
+            else if (x < 2 * n) { lb[i] = a.A.col_ptr[x - n]; le[i] = a.A.col_ptr[x - n + 1]; }
+        }
         const uint32_t d0 = leaves.x & 0xFFFFu, d1 = leaves.x >> 16, d2 = leaves.y & 0xFFFFu,
                        d3 = leaves.y >> 16;
         const int j = d0 == m ? 0 : d1 == m ? 1 : d2 == m ? 2 : d3 == m ? 3 : 4;
         hit = ballot(j < 4);
         if (!hit) return false;
         const int src = __ffsll((unsigned long long)hit) - 1;
-        vsel = 256 * g + 4 * src + read_lane(j, src);
+        const int js = read_lane(j, src);
+        vsel = 256 * g + 4 * src + js;
         gsel = g;
+        const int32_t mb = js == 0 ? lb[0] : js == 1 ? lb[1] : js == 2 ? lb[2] : lb[3];
+        const int32_t me = js == 0 ? le[0] : js == 1 ? le[1] : js == 2 ? le[2] : le[3];
+        vb = read_lane(mb, src);
+        ve = read_lane(me, src);
         return true;
     }
 
@@ -706,22 +722,38 @@ __device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uin
     x[7] = (float)(c2_u < 255 ? c2_u : 255) / 64.0f;
 }
 
-// Neighbourhood statistics of the candidate u held by each lane (cand):
-// s_u = sum over the residual neighbours w of u of floor(2^20 / deg w) and
-// c2_u = #{w != v : deg w <= 2}.  The candidates' lists are flattened over
-// the wave (64 entries per pass) and summed per owner with a segmented scan;
-// integer sums, so the result does not depend on the order.
+// The candidates' flattened lists as read by candidate_stats when they fit
+// one pass of the wave: the step reuses them for N_t(u) once u is drawn.
+struct NbrCache {
+    bool valid = false;   // wave-uniform: all candidate lists fit one pass
+    int32_t off = 0;      // per candidate lane: first flattened lane of its list
+    int32_t ub = 0;       // per candidate lane: its list start
+    int32_t len = 0;      // per candidate lane: its list length
+    int32_t w = -1;       // per flattened lane: the neighbour
+    uint32_t dw = 0;      // its residual degree (kRetired if matched)
+    bool live = false;    // active and the edge not removed
+};
+
+// Neighbourhood statistics of the candidate u held by each lane (cand), whose
+// list [ub, ue) the caller has read: s_u = sum over the residual neighbours w
+// of u of floor(2^20 / deg w) and c2_u = #{w != v : deg w <= 2}.  The
+// candidates' lists are flattened over the wave (64 entries per pass) and
+// summed per owner with a segmented scan; integer sums, so the result does
+// not depend on the order.
 template <class TT>
-__device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t v, uint64_t &s_u, int32_t &c2_u) {
+__device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, int32_t ue, int32_t v,
+                                uint64_t &s_u, int32_t &c2_u, NbrCache &nc) {
     const int l = lane_id();
     const bool u_row = u < T.n;
-    int32_t ub = 0, ue = 0;
-    if (cand) T.list(u, ub, ue);
-    int32_t total;
-    const int32_t off = wave_excl_scan_i32(cand ? ue - ub : 0, total);
     const int32_t len = cand ? ue - ub : 0;
+    int32_t total;
+    const int32_t off = wave_excl_scan_i32(len, total);
     s_u = 0;
     c2_u = 0;
+    nc.valid = total <= kWave;
+    nc.off = off;
+    nc.ub = ub;
+    nc.len = len;
     for (int32_t base = 0; base < total; base += kWave) {
         const int32_t f = base + l;
         const bool valid = f < total;
@@ -731,16 +763,23 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t v, ui
         const bool o_row = __shfl((int)u_row, own) != 0;
         uint32_t sv = 0;
         int32_t cv = 0;
+        int32_t w = -1;
+        uint32_t dw = 0;
+        bool live = false;
         if (valid) {
-            int32_t w, e;
+            int32_t e;
             float bv;
             T.entry(o_row, o_ub + (f - o_off), w, e, bv);
-            const uint32_t dw = T.deg[w];
-            if (dw != kRetired && dw != 0 && !T.removed(e)) {
+            dw = T.deg[w];
+            live = dw != kRetired && !T.removed(e);
+            if (live && dw != 0) {
                 sv = (1u << 20) / dw;
                 cv = (w != v && dw <= 2u) ? 1 : 0;
             }
         }
+        nc.w = w;
+        nc.dw = dw;
+        nc.live = live;
         // inclusive scan within runs of equal owner (runs are contiguous)
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
@@ -762,49 +801,50 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t v, ui
 }
 
 // Logits (units of 1/16) of the candidates held by the lanes of one list
-// chunk: features staged in LDS, the quantised network on matrix cores in
-// 16-lane tiles.  Lanes without a candidate return 0.
-__device__ int32_t learned_logits(const MlpLds *W, char *scratch, bool cand, uint32_t deg_rho,
+// chunk: the quantised network on matrix cores in 16-candidate tiles, the
+// feature tile assembled and the logits returned by cross-lane moves (only
+// the layer-1 activations pass through LDS).  Lanes without a candidate
+// return 0.
+__device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uint32_t deg_rho,
                                   uint32_t deg_gam, float r0_rho, float c0_gam, int32_t t, int32_t n,
                                   bool v_row, uint64_t s_u, int32_t c2_u, int32_t chunk_len) {
     const int l = lane_id();
-    float *feat = reinterpret_cast<float *>(scratch);                    // [64][8]
-    int32_t *logit = reinterpret_cast<int32_t *>(scratch + 64 * 8 * 4);  // [64]
-    TileLds *tile = reinterpret_cast<TileLds *>(scratch + 64 * 8 * 4 + 64 * 4);
     float x[8];
     learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_row, s_u, c2_u);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) feat[l * 8 + k] = cand ? x[k] : 0.0f;
-    wave_fence();
+    for (int k = 0; k < 8; ++k) x[k] = cand ? x[k] : 0.0f;
+    const int grp = l >> 4;  // A-operand features 4 grp .. 4 grp + 3 (grp < 2)
+    int32_t mine = 0;
     const int ntiles = (chunk_len + 15) / 16;
     for (int ti = 0; ti < ntiles; ++ti) {
+        const int src = 16 * ti + (l & 15);
         bf16x4 xa;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = 4 * (l / 16) + j;
-            xa[j] = k < kIn ? to_bf16(feat[(16 * ti + l % 16) * 8 + k]) : (short)0;
+            const float lo = __shfl(x[j], src), hi = __shfl(x[4 + j], src);
+            xa[j] = grp == 0 ? to_bf16(lo) : (grp == 1 ? to_bf16(hi) : (short)0);
         }
         f32x4 z1[4], z2[4];
         float lg[4];
         mlp_tile_forward<true>(W, tile, xa, z1, z2, lg);
-        if (l % 16 == 0) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float L = rintf(lg[j] * 16.0f);
-                L = L < -1024.0f ? -1024.0f : (L > 1023.0f ? 1023.0f : L);
-                logit[16 * ti + 4 * (l / 16) + j] = (int32_t)L;
-            }
+        // row i = l % 16 of the tile sits in lane group i / 4, register i % 4
+        const int row = l & 15, from = 16 * (row >> 2);
+        const float v0 = __shfl(lg[0], from), v1 = __shfl(lg[1], from);
+        const float v2 = __shfl(lg[2], from), v3 = __shfl(lg[3], from);
+        const int js = row & 3;
+        const float y = js == 0 ? v0 : (js == 1 ? v1 : (js == 2 ? v2 : v3));
+        if (grp == ti) {
+            float L = rintf(y * 16.0f);
+            L = L < -1024.0f ? -1024.0f : (L > 1023.0f ? 1023.0f : L);
+            mine = (int32_t)L;
         }
-        wave_fence();
     }
-    const int32_t mine = cand ? logit[l] : 0;
-    wave_fence();
-    return mine;
+    return cand ? mine : 0;
 }
 
 template <int SK, bool DM, bool WT>
 __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT> &T,
-                                               int64_t q, Work &work, const MlpLds *mlpw, char *mlps) {
+                                               int64_t q, Work &work, const MlpLds *mlpw, TileLds *mlps) {
     constexpr bool OWN = OwnRC<SK>::value;
     const int l = lane_id();
     const int32_t n = a.A.n;
@@ -848,17 +888,20 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
         const uint64_t R0 = rand64(a.seed, k, a.b, (uint32_t)t, 0u);
         // ---- choose the vertex
         int32_t v = -1, gsel = -1;
+        int32_t vb = 0, ve = 0;
         uint2 gleaves = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
-        if (a.vertex_rule == 1) v = t;
-        else if (!T.select_min(v, gsel, gleaves)) v = -1;
+        if (a.vertex_rule == 1) {
+            v = t;
+            T.list(v, vb, ve);
+        } else if (!T.select_min(v, gsel, gleaves, vb, ve)) {
+            v = -1;
+        }
         if (v < 0 || v >= 2 * n) {  // internal inconsistency: report, never index
             if (l == 0) atomicOr(a.err, 1u);
             alive = false;
             break;
         }
         const bool v_row = v < n;
-        int32_t vb, ve;
-        T.list(v, vb, ve);
         const bool fast_v = ve - vb <= kWave;
 
         // ---- candidates N_t(v), proposal of Eq. (q), draw, pick
@@ -869,14 +912,19 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
         int32_t cy = -1;   // this lane's candidate (lists up to a wave)
         uint32_t cd = 0;
         bool cand = false;
+        NbrCache nc;       // learned: the candidates' lists, reused for N_t(u)
+        int u_lane = -1;   // fast path: the lane that held u
+        int32_t u_ub = 0, u_ue = 0;  // fast path: u's list bounds
         if (fast_v) {
             const int32_t p = vb + l;
             int32_t e = 0;
             float bv = 0.0f, sc = 1.0f;
+            int32_t cub = 0, cue = 0;
             if (p < ve) {
                 T.entry(v_row, p, cy, e, bv);
                 cd = T.deg[cy];
                 if (a.scaled) sc = T.scale(cy);
+                T.list(cy, cub, cue);  // issued with the degree load; u's list comes from here
                 cand = cd != kRetired && !T.removed(e);
             }
             kc = __popcll(ballot(cand));
@@ -893,7 +941,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                     const float c0g = a.c0 ? a.c0[cand ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
-                    candidate_stats(T, cand, cy, v, su, c2);
+                    candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc);
                     L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
                                        t, n, v_row, su, c2, ve - vb);
                     work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
@@ -937,7 +985,10 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                     const float ssum = wave_sum_f32(cand ? s : 0.0f);
                     uint64_t su;
                     int32_t c2;
-                    candidate_stats(T, cand, cy, v, su, c2);
+                    int32_t rub = 0, rue = 0;
+                    if (cand) T.list(cy, rub, rue);
+                    NbrCache rnc;
+                    candidate_stats(T, cand, cy, rub, rue, v, su, c2, rnc);
                     unsigned long long old = 0;
                     if (l == 0) {
                         const unsigned long long cur = __hip_atomic_load(a.rec_counter, __ATOMIC_RELAXED,
@@ -986,6 +1037,9 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 b_vu = read_lane(bv, src);
                 w_u = read_lane(w, src);
                 d_u = read_lane(cd, src);
+                u_ub = read_lane(cub, src);
+                u_ue = read_lane(cue, src);
+                u_lane = src;
             }
             if (kc == 1) W = w_u;
         } else {
@@ -1032,7 +1086,10 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                     const float c0g = a.c0 ? a.c0[c0 ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
-                    candidate_stats(T, c0, y, v, su, c2);
+                    int32_t yub = 0, yue = 0;
+                    if (c0) T.list(y, yub, yue);
+                    NbrCache lnc;
+                    candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc);
                     const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
                                                      v_row ? dy : (uint32_t)kc, r0r, c0g, t, n, v_row, su, c2,
                                                      min(kWave, ve - base));
@@ -1136,14 +1193,35 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
 
         // ---- N_t(u) \ {v}
         int32_t ub, ue;
-        T.list(u, ub, ue);
+        // learned: u's list, its neighbours and their degrees were read for
+        // the features (nothing has changed since); move them into place
+        const bool from_cache = SK == kSkLearned && nc.valid && u_lane >= 0;
+        int32_t u_off = 0;
+        if (from_cache) u_off = read_lane(nc.off, u_lane);
+        if (u_lane >= 0) {
+            ub = u_ub;
+            ue = u_ue;
+        } else {
+            T.list(u, ub, ue);
+        }
         const bool fast_u = ue - ub <= kWave;
         const bool u_row = u < n;
         int32_t by = -1;
         uint32_t bd = 0;
         bool take = false;
         int32_t kb = 0;
-        if (fast_u) {
+        if (from_cache) {
+            const int srcl = (u_off + l) & (kWave - 1);
+            const int32_t w2 = __shfl(nc.w, srcl);
+            const uint32_t d2 = __shfl(nc.dw, srcl);
+            const bool live2 = __shfl((int)nc.live, srcl) != 0;
+            if (ub + l < ue) {
+                by = w2;
+                bd = d2;
+                take = by != v && live2;
+            }
+            kb = __popcll(ballot(take));
+        } else if (fast_u) {
             const int32_t p = ub + l;
             if (p < ue) {
                 int32_t e; float bv;
@@ -1326,17 +1404,17 @@ struct BatchArgs {
     const float *mlp;         // learned proposal parameters (staged per block), or nullptr
 };
 
-constexpr int kMlpWaveBytes = 64 * 8 * 4 + 64 * 4 + (int)sizeof(TileLds);
+constexpr int kMlpWaveBytes = (int)sizeof(TileLds);
 constexpr int kMlpBlockBytes = ((int)sizeof(MlpLds) + 15) / 16 * 16;
 
 // The argument blocks live in device memory (uniform fields become scalar
 // loads; no private copy of a by-value parameter is needed).
 template <int SK, bool DM, bool WT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || (!DM && SK != kSkLearned)) ? 4 : 1, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || !DM) ? 4 : 1, 8)))
 traj_kernel(const BatchArgs *__restrict__ bp) {
     const BatchArgs &B = *bp;
     extern __shared__ __align__(16) char smem[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
     // block: [network weights (learned)] then per wave [tree | network tiles | state]
     MlpLds *mlpw = reinterpret_cast<MlpLds *>(smem);
     char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
@@ -1347,7 +1425,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)B.lds_state_bytes;
     char *mine = waves + (size_t)wave * per_wave;
     uint32_t *tree = reinterpret_cast<uint32_t *>(mine);
-    char *mlps = mine + B.lds_tree_bytes;
+    TileLds *mlps = reinterpret_cast<TileLds *>(mine + B.lds_tree_bytes);
     char *state;
     if (B.hbm_state) {
         const uint64_t slot = (uint64_t)blockIdx.x * B.waves_per_block + wave;

@@ -191,16 +191,22 @@ int perm_est_create_batch(int32_t count, const int32_t *n, const int64_t *nnz,
                               per CU) by timing candidates on a probe slice
                               the first time a schedule kind is run; results
                               do not depend on the shape                     */
+#define PE_RUN_GRAPH 2     /* run the launch sequence (counter clears,
+                              persistent trajectory kernel, reduction) as a
+                              HIP graph captured once per launch shape and
+                              replayed; per-run values (seed, counts, output
+                              pointers) are uploaded before each replay.
+                              Results are identical to an eager run          */
 
 /* Run trajectories 0..n_traj[b]-1 of every matrix b of a batch handle in one
  * persistent launch (Alg. 2 per trajectory, matrix b uses counter word b)
- * and reduce each matrix separately.
+ * and reduce each matrix separately (one reduction launch for all).
  *   n_traj:    host int64[count], each in [1, 2^32).
  *   res:       host perm_est_result[count]; the work-unit fields and
  *              `seconds` describe the whole launch.
  *   logw, alive, path_hash: device arrays of sum(n_traj) entries (matrix b
  *              at offset sum_{c<b} n_traj[c]), or NULL.
- *   flags:     PE_RUN_AUTOTUNE or 0.
+ *   flags:     PE_RUN_AUTOTUNE and/or PE_RUN_GRAPH, or 0.
  * Errors: PE_EINVAL, PE_ENOTSUP, PE_ENOMEM, PE_EDEVICE. */
 int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed,
                        const perm_est_schedule *sched, perm_est_result *res,

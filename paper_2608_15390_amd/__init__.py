@@ -164,7 +164,7 @@ class PermEstBatch(_ModelMixin):
             pass
 
     def run(self, n_traj, seed: int, schedule: N.Schedule, *, want_logw=True, want_alive=True,
-            want_hash=False, autotune=False, stream=None) -> Dict:
+            want_hash=False, autotune=False, graph=False, stream=None) -> Dict:
         """n_traj: an int (same for every matrix) or one count per matrix.
         Returns per-matrix statistics and the concatenated device outputs."""
         import torch
@@ -179,7 +179,8 @@ class PermEstBatch(_ModelMixin):
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         N.check(self._lib.perm_est_run_batch(
             self._h, counts.ctypes.data, C.c_uint64(seed), C.byref(schedule), res,
-            _ptr(logw), _ptr(alive), _ptr(ph), N.PE_RUN_AUTOTUNE if autotune else 0,
+            _ptr(logw), _ptr(alive), _ptr(ph),
+            (N.PE_RUN_AUTOTUNE if autotune else 0) | (N.PE_RUN_GRAPH if graph else 0),
             C.c_void_p(st.cuda_stream)))
         out = {"results": [r.as_dict() for r in res], "offsets": np.concatenate([[0], np.cumsum(counts)])}
         for k, v in (("logw", logw), ("alive", alive), ("path_hash", ph)):

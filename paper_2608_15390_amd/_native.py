@@ -96,6 +96,7 @@ EXPORTS = [
 
 PE_FLAG_FORCE_HBM = 1
 PE_RUN_AUTOTUNE = 1
+PE_RUN_GRAPH = 2
 PE_SK_LEARNED = 4
 PE_MLP_NPARAM = 4801
 

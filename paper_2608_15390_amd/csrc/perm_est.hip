@@ -126,7 +126,8 @@ struct perm_est {
     TrajArgs *args_dev = nullptr;
     BatchArgs *batch_dev = nullptr;
     int32_t *order_dev = nullptr;
-    int64_t *item_off_dev = nullptr, *seg_dev = nullptr;
+    int64_t *item_off_dev = nullptr;
+    ReduceSeg *seg_dev = nullptr;
     DevStats *stats = nullptr;
     size_t cap_mats = 0;
     double *tmp_logw = nullptr;
@@ -140,11 +141,22 @@ struct perm_est {
     double mix_alpha = 0.05;
     bool has_model = false;
     unsigned long long *rec_ctr = nullptr;  // [0] claimed, [1] written (records << 32 | groups)
+    // captured launch sequence (counter fills, trajectory kernel, reduction);
+    // its kernels read every per-run value from device memory uploaded before
+    // each replay, so one capture serves every run with the same launch shape
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_fn = nullptr;
+    unsigned graph_blocks = 0, graph_threads = 0;
+    size_t graph_shmem = 0;
+    bool graph_res = false;
     // host copies the async uploads read from
     std::vector<TrajArgs> args_host;
     BatchArgs batch_host{};
     std::vector<int32_t> order_host;
-    std::vector<int64_t> item_off_host, seg_host;
+    std::vector<int64_t> item_off_host;
+    std::vector<ReduceSeg> seg_host;
 };
 
 namespace {
@@ -534,7 +546,7 @@ int grow_mats(perm_est *h, size_t count) {
     h->cap_mats = 0;
     int rc;
     if ((rc = dalloc(&h->args_dev, count)) || (rc = dalloc(&h->order_dev, count)) ||
-        (rc = dalloc(&h->item_off_dev, count + 1)) || (rc = dalloc(&h->seg_dev, 2 * count)) ||
+        (rc = dalloc(&h->item_off_dev, count + 1)) || (rc = dalloc(&h->seg_dev, count)) ||
         (rc = dalloc(&h->stats, count)))
         return rc;
     h->cap_mats = count;
@@ -546,7 +558,7 @@ int grow_mats(perm_est *h, size_t count) {
 // outputs go to scratch buffers.  rec: training-pair recording, or nullptr.
 int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vector<RunPart> &parts,
            perm_est_result *res, hipStream_t s, int wpb_req, int per_cu_req, double *elapsed_ms,
-           const perm_est_record_buffers *rec = nullptr) {
+           const perm_est_record_buffers *rec = nullptr, bool graph = false) {
     const size_t count = h->mats.size();
     int rc;
     if ((rc = grow_mats(h, count))) return rc;
@@ -657,8 +669,11 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     h->item_off_host.assign(count + 1, 0);
     for (size_t i = 0; i < count; ++i) h->item_off_host[i + 1] = h->item_off_host[i] + parts[h->order_host[i]].count;
     // each matrix reduces its own slice: segment (0, count_b) per matrix
-    h->seg_host.assign(2 * count, 0);
-    for (size_t b = 0; b < count; ++b) h->seg_host[2 * b + 1] = parts[b].count;
+    h->seg_host.resize(count);
+    for (size_t b = 0; b < count; ++b) {
+        const TrajArgs &a = h->args_host[b];
+        h->seg_host[b] = ReduceSeg{a.logw, a.alive, a.counters, a.count};
+    }
 
     // ---- tier and launch shape
     const size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
@@ -720,22 +735,49 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipMemcpyAsync(h->order_dev, h->order_host.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
     PE_HIP(hipMemcpyAsync(h->item_off_dev, h->item_off_host.data(), sizeof(int64_t) * (count + 1),
                           hipMemcpyHostToDevice, s));
-    PE_HIP(hipMemcpyAsync(h->seg_dev, h->seg_host.data(), sizeof(int64_t) * 2 * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(h->seg_dev, h->seg_host.data(), sizeof(ReduceSeg) * count, hipMemcpyHostToDevice, s));
     PE_HIP(hipMemcpyAsync(h->batch_dev, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
-    k_set_u32<<<1, 1, 0, s>>>(h->work, 0u);
-    k_set_u32<<<1, 1, 0, s>>>(h->work + 1, 0u);
-    k_fill_i32<<<1, 64, 0, s>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
-    if (rec) k_fill_i32<<<1, 64, 0, s>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
-    PE_HIP(hipEventRecord(h->ev0, s));
-    launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, s, h->batch_dev);
-    PE_HIP(hipGetLastError());
-    if (res) {
-        // per-matrix statistics over each matrix's slice of the outputs
-        for (size_t b = 0; b < count; ++b) {
-            const TrajArgs &a = h->args_host[b];
-            k_reduce_stats<<<1, 1024, 0, s>>>(a.logw, a.alive, a.counters, h->seg_dev + 2 * b, h->stats + b);
-        }
+    // the launch sequence; counters are cleared by kernels (no memset nodes)
+    auto enqueue = [&](hipStream_t q) -> int {
+        k_set_u32<<<1, 1, 0, q>>>(h->work, 0u);
+        k_set_u32<<<1, 1, 0, q>>>(h->work + 1, 0u);
+        k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
+        if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
+        launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
         PE_HIP(hipGetLastError());
+        // per-matrix statistics over each matrix's slice of the outputs
+        if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(h->seg_dev, h->stats);
+        PE_HIP(hipGetLastError());
+        return PE_OK;
+    };
+    if (graph && !rec) {
+        const void *fn = traj_kernel_fn(sched->sk_policy, dm, wt);
+        const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
+                          h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
+                          h->graph_res == (res != nullptr);
+        if (!same) {
+            if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+            if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+            if (!h->cap_stream) PE_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            PE_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int erc = enqueue(h->cap_stream);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
+            if (erc) { if (g) (void)hipGraphDestroy(g); return erc; }
+            if (ce != hipSuccess) return fail(PE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+            h->graph = g;
+            PE_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+            h->graph_fn = fn;
+            h->graph_blocks = blocks;
+            h->graph_threads = (unsigned)(wpb * kWave);
+            h->graph_shmem = shmem;
+            h->graph_res = res != nullptr;
+        }
+        PE_HIP(hipEventRecord(h->ev0, s));
+        PE_HIP(hipGraphLaunch(h->graph_exec, s));
+    } else {
+        PE_HIP(hipEventRecord(h->ev0, s));
+        if ((rc = enqueue(s))) return rc;
     }
     PE_HIP(hipEventRecord(h->ev1, s));
     std::vector<DevStats> st(count);
@@ -1008,6 +1050,9 @@ void perm_est_destroy(perm_est_t *h) {
     dfree(h->args_dev); dfree(h->order_dev); dfree(h->item_off_dev); dfree(h->seg_dev); dfree(h->stats);
     dfree(h->tmp_logw); dfree(h->tmp_alive); dfree(h->tmp_counters);
     dfree(h->mlp); dfree(h->etab); dfree(h->rec_ctr);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -1040,7 +1085,7 @@ int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed, cons
                        perm_est_result *res, double *logw, uint8_t *alive, uint64_t *path_hash,
                        int32_t flags, void *stream) {
     if (!h || !res || !n_traj) return fail(PE_EINVAL, "null handle, result or n_traj");
-    if (flags & ~PE_RUN_AUTOTUNE) return fail(PE_EINVAL, "unknown run flags");
+    if (flags & ~(PE_RUN_AUTOTUNE | PE_RUN_GRAPH)) return fail(PE_EINVAL, "unknown run flags");
     int rc;
     if ((rc = check_schedule(sched))) return rc;
     PE_HIP(hipSetDevice(h->device));
@@ -1060,7 +1105,7 @@ int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed, cons
     hipStream_t s = (hipStream_t)stream;
     if (flags & PE_RUN_AUTOTUNE)
         if ((rc = tuned_shape(h, sched, seed, parts, s, &wpb, &per_cu))) return rc;
-    return launch(h, sched, seed, parts, res, s, wpb, per_cu, nullptr);
+    return launch(h, sched, seed, parts, res, s, wpb, per_cu, nullptr, nullptr, (flags & PE_RUN_GRAPH) != 0);
 }
 
 int perm_est_set_model(perm_est_t *h, const float *params, double mix_alpha, void *stream) {

@@ -4,13 +4,21 @@
 //   L  = max ln X over survivors, S1 = sum e^{lnX - L}, S2 = sum e^{2(lnX-L)}
 //   ln mean = L + ln S1 - ln M; CV^2 = M (M S2 / S1^2 - 1) / (M - 1);
 //   RSE = CV / sqrt(M); ESS = S1^2 / S2; p_match = n_alive / M.
-// One block per segment (matrix); each thread owns a strided subset and
-// the block combines partials in a fixed tree order, so results do not
-// depend on scheduling.
+// One block per segment (matrix), all segments in one launch; each thread
+// owns a strided subset and the block combines partials in a fixed tree
+// order, so results do not depend on scheduling.
 #pragma once
 #include "device.hpp"
 
 namespace pe {
+
+// one matrix's per-trajectory outputs
+struct ReduceSeg {
+    const double *logw;
+    const uint8_t *alive;
+    const int32_t *counters;  // [count][4] or nullptr
+    int64_t count;
+};
 
 struct DevStats {
     double log_estimate, p_match, rel_spread, rse, ess, var_logw, max_logw;
@@ -42,12 +50,14 @@ __device__ T block_reduce(T v, T *buf, Op op) {
     return r;
 }
 
-__global__ void __launch_bounds__(1024) k_reduce_stats(const double *logw, const uint8_t *alive,
-                                                      const int32_t *counters, const int64_t *seg_off,
-                                                      DevStats *out) {
+__global__ void __launch_bounds__(1024) k_reduce_stats(const ReduceSeg *segs, DevStats *out) {
     __shared__ double dbuf[1024];
     __shared__ long long ibuf[1024];
-    const int64_t lo = seg_off[blockIdx.x], hi = seg_off[blockIdx.x + 1];
+    const ReduceSeg sg = segs[blockIdx.x];
+    const double *logw = sg.logw;
+    const uint8_t *alive = sg.alive;
+    const int32_t *counters = sg.counters;
+    const int64_t lo = 0, hi = sg.count;
     const int t = threadIdx.x, B = blockDim.x;
     auto dmax = [](double a, double b) { return a > b ? a : b; };
     auto dadd = [](double a, double b) { return a + b; };

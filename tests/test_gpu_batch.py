@@ -115,3 +115,28 @@ def test_batch_estimates_unbiased_on_known_permanents():
     for r, per in zip(out["results"], pers):
         assert abs(math.exp(r["log_estimate"]) / per - 1) <= 4.5 * r["rse"]
     bt.close()
+
+
+def test_graph_replays_equal_eager_runs():
+    """The captured launch sequence replays to the eager results on every
+    replay, with eager launches of other seeds and shapes in between."""
+    import paper_2608_15390_amd as P
+    mats = _small_batch(count=5, seed=12)
+    sched = P.preset("adaptive_threshold")
+    bt = P.PermEstBatch(mats)
+    counts = [200 + 13 * b for b in range(len(mats))]
+    for rep, seed in enumerate((3, 4, 3, 9)):
+        print(f"[gpu] graph replay {rep} seed {seed}", flush=True)
+        g = bt.run(counts, seed, sched, want_hash=True, graph=True)
+        torch.cuda.synchronize()
+        other = bt.run(17, seed + 100, P.preset("plain"), want_hash=True)  # eager work in between
+        torch.cuda.synchronize()
+        e = bt.run(counts, seed, sched, want_hash=True)
+        torch.cuda.synchronize()
+        for k in ("logw", "alive", "path_hash"):
+            assert torch.equal(g[k], e[k]), (rep, k)
+        for rg, re_ in zip(g["results"], e["results"]):
+            for f in ("log_estimate", "ess", "p_match", "n_alive", "n_steps"):
+                assert rg[f] == re_[f] or (math.isnan(rg[f]) and math.isnan(re_[f])), (rep, f)
+        assert other["results"][0]["n_traj"] == 17
+    bt.close()

@@ -276,3 +276,36 @@ def test_recorded_pairs_match_the_oracle():
                                     float(pre.c[gam - n]), t, n, int(v_row), S, c2)
             np.testing.assert_array_equal(x[sl][i], np.asarray(fr, dtype=np.float32), err_msg=str((b, k, t, i)))
     bt.close()
+
+
+def test_stress_power_law_batch_learned_sampled():
+    """Power-law degrees (exponent 2.5 on [2, 200], planted permutation), n
+    from 1e4 to 4e4, learned proposal, one autotuned graph-replayed batch
+    launch: sampled (matrix, trajectory) pairs are recomputed one by one by
+    the oracle."""
+    import paper_2608_15390_amd as P
+    mats = [G.power_law(n, 100 + i) for i, n in enumerate((10000, 20000, 40000))]
+    model = R.quantize(R.init(31, scale=1.5))
+    sched = P.preset("learned")
+    print(f"[gpu] stress batch n={[M.n for M in mats]} max deg {[int(np.diff(M.row_ptr).max()) for M in mats]}",
+          flush=True)
+    bt = P.PermEstBatch(mats)
+    bt.set_model(_dev(model, torch.float32), 0.01)
+    out = bt.run(128, 5, sched, want_hash=True, autotune=True, graph=True)
+    torch.cuda.synchronize()
+    lw = out["logw"].cpu().numpy()
+    al = out["alive"].cpu().numpy()
+    ph = out["path_hash"].cpu().numpy().view(np.uint64)
+    osch = _osched(sched, model, 0.01)
+    rng = np.random.default_rng(1)
+    for b, M in enumerate(mats):
+        A = O.OMatrix(M)
+        pre = O.prep(A, osch)
+        for k in sorted(rng.choice(128, 2, replace=False)):
+            o = O.run(A, osch, seed=5, first=int(k), count=1, b=b, pre=pre)
+            q = 128 * b + int(k)
+            assert al[q] == o["alive"][0] and ph[q] == o["path_hash"][0], (b, k)
+            if o["alive"][0]:
+                assert lw[q] == pytest.approx(o["logw"][0], rel=1e-12)
+        assert 0.0 <= out["results"][b]["p_match"] <= 1.0
+    bt.close()

@@ -49,52 +49,85 @@ __device__ __forceinline__ T read_lane(T v, int src) {
 template <typename T>
 __device__ __forceinline__ T uniform(T v) { return read_lane(v, 0); }
 
+// ------------------------------------------------------------ DPP
+// Cross-lane data movement by DPP (data-parallel primitives: operands read
+// from another lane of the same VGPR in the same VALU instruction), no LDS
+// crossbar.  A lane whose source lies outside its row, or whose row is
+// masked off, receives `old` (bound_ctrl off).
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive scan in lane order for an associative op with identity `id`:
+// four shifted steps within each 16-lane row, then the last lane of row 0
+// (and of row 2) is added to row 1 (row 3), then lane 31 to rows 2 and 3.
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x, uint32_t id, Op op) {
+    x = op(x, dpp<kRowShr1>(id, x));
+    x = op(x, dpp<kRowShr2>(id, x));
+    x = op(x, dpp<kRowShr4>(id, x));
+    x = op(x, dpp<kRowShr8>(id, x));
+    x = op(x, dpp<kRowBcast15, 0xA>(id, x));
+    x = op(x, dpp<kRowBcast31, 0xC>(id, x));
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t y = __shfl_xor(x, o);
-        x = y < x ? y : x;
-    }
-    return uniform(x);
+    const uint32_t r = wave_scan_u32(x, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return b < a ? b : a; });
+    return read_lane(r, kWave - 1);
 }
 
+// plain comparisons (no fmaxf), so a NaN from another lane never wins
 __device__ __forceinline__ float wave_max_f32(float x) {
-    // plain comparisons (no fmaxf) so NaNs never win, as in a sequential max
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        float y = __shfl_xor(x, o);
-        x = (y > x) ? y : x;
-    }
-    return uniform(x);
+    const uint32_t r = wave_scan_u32(__float_as_uint(x), __float_as_uint(-__builtin_huge_valf()),
+                                     [](uint32_t a, uint32_t b) {
+                                         const float fa = __uint_as_float(a), fb = __uint_as_float(b);
+                                         return fb > fa ? b : a;
+                                     });
+    return __uint_as_float(read_lane(r, kWave - 1));
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return uniform(x);
+__device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
+    const uint32_t r = wave_scan_u32((uint32_t)x, 0x80000000u, [](uint32_t a, uint32_t b) {
+        return (int32_t)b > (int32_t)a ? b : a;
+    });
+    return (int32_t)read_lane(r, kWave - 1);
 }
 
-__device__ __forceinline__ float wave_sum_f32(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return uniform(x);
+// inclusive prefix sum over the 64 lanes in lane order (exact, 64-bit)
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    auto step = [&](uint32_t ylo, uint32_t yhi) {
+        const uint32_t s = lo + ylo;
+        hi = hi + yhi + (s < lo ? 1u : 0u);
+        lo = s;
+    };
+    step(dpp<kRowShr1>(0u, lo), dpp<kRowShr1>(0u, hi));
+    step(dpp<kRowShr2>(0u, lo), dpp<kRowShr2>(0u, hi));
+    step(dpp<kRowShr4>(0u, lo), dpp<kRowShr4>(0u, hi));
+    step(dpp<kRowShr8>(0u, lo), dpp<kRowShr8>(0u, hi));
+    step(dpp<kRowBcast15, 0xA>(0u, lo), dpp<kRowBcast15, 0xA>(0u, hi));
+    step(dpp<kRowBcast31, 0xC>(0u, lo), dpp<kRowBcast31, 0xC>(0u, hi));
+    return ((uint64_t)hi << 32) | lo;
 }
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) { return read_lane(wave_incl_scan_u64(x), kWave - 1); }
 
 __device__ __forceinline__ int wave_sum_i32(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return uniform(x);
+    const uint32_t r = wave_scan_u32((uint32_t)x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+    return (int)read_lane(r, kWave - 1);
 }
 
-// inclusive prefix sum over the 64 lanes in lane order
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint64_t y = __shfl_up(x, o);
-        if (l >= o) x += y;
-    }
-    return x;
+// float sum in the scan's fixed combination order
+__device__ __forceinline__ float wave_sum_f32(float x) {
+    const uint32_t r = wave_scan_u32(__float_as_uint(x), 0u, [](uint32_t a, uint32_t b) {
+        return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+    });
+    return __uint_as_float(read_lane(r, kWave - 1));
 }
 
 // number of set bits of `mask` strictly below this lane

@@ -83,7 +83,8 @@ struct TileLds {
 // QUANT: re-quantise the ReLU outputs onto the 1/64 grid [0, 255/64]
 // (inference); otherwise plain ReLU (training).  Outputs in D layout:
 // z1[nt], z2[nt] (pre-activations, column 16 nt + l % 16, rows
-// 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (valid in every lane).
+// 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (complete in the
+// last lane of each 16-lane group, l % 16 == 15).
 template <bool QUANT>
 __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf16x4 xa, f32x4 z1[4],
                                                  f32x4 z2[4], float logit[4]) {
@@ -134,13 +135,17 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         }
         z2[nt] = acc;
     }
-    // layer 3: sum the 64 columns over the 16 lanes of each row group
+    // layer 3: sum the 64 columns over the 16 lanes of each row group (a
+    // row-shifted DPP scan: the group total lands in its last lane)
+    auto fadd = [](uint32_t a, uint32_t b) { return __float_as_uint(__uint_as_float(a) + __uint_as_float(b)); };
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        float v = part[j];
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) v = v + __shfl_xor(v, o);
-        logit[j] = v + W->b3;
+        uint32_t v = __float_as_uint(part[j]);
+        v = fadd(v, dpp<kRowShr1>(0u, v));
+        v = fadd(v, dpp<kRowShr2>(0u, v));
+        v = fadd(v, dpp<kRowShr4>(0u, v));
+        v = fadd(v, dpp<kRowShr8>(0u, v));
+        logit[j] = __uint_as_float(v) + W->b3;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
@@ -170,7 +175,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *P, const float
         f32x4 z1[4], z2[4];
         float lg[4];
         mlp_tile_forward<false>(&W, &tiles[wave], load_x_tile(X, n, 16 * t), z1, z2, lg);
-        if (l % 16 == 0)
+        if (l % 16 == 15)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t row = 16 * t + 4 * (l / 16) + j;

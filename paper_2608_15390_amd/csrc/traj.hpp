@@ -497,15 +497,9 @@ __device__ __forceinline__ int owner_lane(int32_t f, int32_t off) {
 }
 
 __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total) {
-    const int l = lane_id();
-    int32_t v = x;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t y = __shfl_up(v, o);
-        if (l >= o) v += y;
-    }
-    total = __shfl(v, kWave - 1);
-    return v - x;
+    const uint32_t incl = wave_scan_u32((uint32_t)x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+    total = (int32_t)read_lane(incl, kWave - 1);
+    return (int32_t)incl - x;
 }
 
 // Eq. (local).  rho_y: a column vertex of N_t(rho)\{gam} held by this lane
@@ -780,14 +774,19 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, i
         nc.w = w;
         nc.dw = dw;
         nc.live = live;
-        // inclusive scan within runs of equal owner (runs are contiguous)
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint32_t ys = __shfl_up(sv, o);
-            const int32_t yc = __shfl_up(cv, o);
-            const int yo = __shfl_up(own, o);
-            if (l >= o && yo == own) { sv += ys; cv += yc; }
-        }
+        // inclusive scan within runs of equal owner (runs are contiguous, so
+        // a lane adds a shifted partial exactly when it carries its own key)
+        auto seg = [&](uint32_t ys, uint32_t yc, uint32_t yo) {
+            if ((int)yo == own) { sv += ys; cv += (int32_t)yc; }
+        };
+        seg(dpp<kRowShr1>(0u, sv), dpp<kRowShr1>(0u, (uint32_t)cv), dpp<kRowShr1>(~0u, (uint32_t)own));
+        seg(dpp<kRowShr2>(0u, sv), dpp<kRowShr2>(0u, (uint32_t)cv), dpp<kRowShr2>(~0u, (uint32_t)own));
+        seg(dpp<kRowShr4>(0u, sv), dpp<kRowShr4>(0u, (uint32_t)cv), dpp<kRowShr4>(~0u, (uint32_t)own));
+        seg(dpp<kRowShr8>(0u, sv), dpp<kRowShr8>(0u, (uint32_t)cv), dpp<kRowShr8>(~0u, (uint32_t)own));
+        seg(dpp<kRowBcast15, 0xA>(0u, sv), dpp<kRowBcast15, 0xA>(0u, (uint32_t)cv),
+            dpp<kRowBcast15, 0xA>(~0u, (uint32_t)own));
+        seg(dpp<kRowBcast31, 0xC>(0u, sv), dpp<kRowBcast31, 0xC>(0u, (uint32_t)cv),
+            dpp<kRowBcast31, 0xC>(~0u, (uint32_t)own));
         // each candidate lane takes the scan value at the last lane of its run
         const int32_t lo_f = off > base ? off : base;
         int32_t hi_f = off + len;
@@ -827,8 +826,8 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
         f32x4 z1[4], z2[4];
         float lg[4];
         mlp_tile_forward<true>(W, tile, xa, z1, z2, lg);
-        // row i = l % 16 of the tile sits in lane group i / 4, register i % 4
-        const int row = l & 15, from = 16 * (row >> 2);
+        // row i = l % 16 of the tile: lane group i / 4 (its last lane), register i % 4
+        const int row = l & 15, from = 16 * (row >> 2) + 15;
         const float v0 = __shfl(lg[0], from), v1 = __shfl(lg[1], from);
         const float v2 = __shfl(lg[2], from), v3 = __shfl(lg[3], from);
         const int js = row & 3;
@@ -946,12 +945,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                                        t, n, v_row, su, c2, ve - vb);
                     work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
                 }
-                int32_t lmx = cand ? L : -2147483647;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const int32_t y2 = __shfl_xor(lmx, o);
-                    lmx = y2 > lmx ? y2 : lmx;
-                }
+                const int32_t lmx = wave_max_i32(cand ? L : -2147483647);
                 int64_t E = 0;
                 if (cand) {
                     const int32_t d = lmx - L;
@@ -1098,11 +1092,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                     if (c0) { T.lst_b[idx0 + rank_below(msk)] = L; lmx = L > lmx ? L : lmx; }
                     idx0 += __popcll(msk);
                 }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const int32_t y2 = __shfl_xor(lmx, o);
-                    lmx = y2 > lmx ? y2 : lmx;
-                }
+                lmx = wave_max_i32(lmx);
                 wave_fence();
                 uint64_t part = 0;
                 for (int32_t idx = l; idx < kc; idx += kWave) {

@@ -50,6 +50,13 @@ struct MlpLds {
     float b3;
 };
 
+// The sampling side's LDS block: the network plus the integer softmax
+// table E[d] (values <= 2^24, so 32 bits hold them).
+struct LearnedLds {
+    MlpLds net;
+    uint32_t etab[kEtabN];
+};
+
 // position of W2[r][c] in MlpLds::w2
 __device__ __forceinline__ int w2_index(int r, int c) {
     const int ks = r >> 4, nt = c >> 4, lane = 16 * ((r & 15) >> 2) + (c & 15);

@@ -692,6 +692,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.lds_tree_bytes = (int32_t)tree_bytes;
     B.lds_mlp_bytes = learned ? kMlpWaveBytes : 0;
     B.mlp = learned ? h->mlp : nullptr;
+    B.etab = learned ? h->etab : nullptr;
     const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     int wpb = wpb_req > 0 ? wpb_req : 4;
     size_t per_wave = tree_bytes + (size_t)B.lds_mlp_bytes + (lds ? state_bytes : 0);

@@ -843,7 +843,9 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
 
 template <int SK, bool DM, bool WT>
 __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT> &T,
-                                               int64_t q, Work &work, const MlpLds *mlpw, TileLds *mlps) {
+                                               int64_t q, Work &work, const LearnedLds *lrn, TileLds *mlps) {
+    const MlpLds *mlpw = &lrn->net;
+    const uint32_t *etab = lrn->etab;
     constexpr bool OWN = OwnRC<SK>::value;
     const int l = lane_id();
     const int32_t n = a.A.n;
@@ -884,7 +886,6 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
     bool alive = a.ok0 != 0;
 
     for (int32_t t = 0; alive && t < n; ++t) {
-        const uint64_t R0 = rand64(a.seed, k, a.b, (uint32_t)t, 0u);
         // ---- choose the vertex
         int32_t v = -1, gsel = -1;
         int32_t vb = 0, ve = 0;
@@ -949,7 +950,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 int64_t E = 0;
                 if (cand) {
                     const int32_t d = lmx - L;
-                    E = d < kEtabN ? a.etab[d] : 0;
+                    E = d < kEtabN ? (int64_t)etab[d] : 0;
                 }
                 const int64_t S = (int64_t)wave_sum_u64((uint64_t)E);
                 if (cand) {
@@ -1023,7 +1024,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
             }
             const uint64_t incl = wave_incl_scan_u64(w);
             W = read_lane(incl, kWave - 1);
-            const uint64_t j = kc > 1 ? lemire_from(R0, W, a.seed, k, a.b, (uint32_t)t) : 0ull;
+            const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), W, a.seed, k, a.b, (uint32_t)t) : 0ull;
             const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
             if (hm) {
                 const int src = __ffsll((unsigned long long)hm) - 1;
@@ -1097,7 +1098,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 uint64_t part = 0;
                 for (int32_t idx = l; idx < kc; idx += kWave) {
                     const int32_t d = lmx - T.lst_b[idx];
-                    part += d < kEtabN ? (uint64_t)a.etab[d] : 0ull;
+                    part += d < kEtabN ? (uint64_t)etab[d] : 0ull;
                 }
                 Ssum = (int64_t)wave_sum_u64(part);
             }
@@ -1106,7 +1107,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 if (SK == kSkLearned) {
                     if (kc == 1) return 1ull;
                     const int32_t d = lmx - T.lst_b[ci];
-                    const int64_t E = d < kEtabN ? a.etab[d] : 0;
+                    const int64_t E = d < kEtabN ? (int64_t)etab[d] : 0;
                     const double qq = (1.0 - a.mix_alpha) * (double)E / (double)Ssum + a.mix_alpha / (double)kc;
                     const double rr = rint(16777216.0 * qq);
                     return rr >= 1.0 ? (uint64_t)rr : 1ull;
@@ -1132,7 +1133,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 cbase += __popcll(msk);
                 W += wave_sum_u64(w);
             }
-            const uint64_t j = kc > 1 ? lemire_from(R0, W, a.seed, k, a.b, (uint32_t)t) : 0ull;
+            const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), W, a.seed, k, a.b, (uint32_t)t) : 0ull;
             uint64_t pre = 0;
             cbase = 0;
             for (int32_t base = vb; base < ve; base += kWave) {
@@ -1392,10 +1393,11 @@ struct BatchArgs {
     int32_t lds_state_bytes;  // LDS tier: bytes of state per wave
     int32_t waves_per_block;
     const float *mlp;         // learned proposal parameters (staged per block), or nullptr
+    const int64_t *etab;      // learned proposal's softmax table (staged per block)
 };
 
 constexpr int kMlpWaveBytes = (int)sizeof(TileLds);
-constexpr int kMlpBlockBytes = ((int)sizeof(MlpLds) + 15) / 16 * 16;
+constexpr int kMlpBlockBytes = ((int)sizeof(LearnedLds) + 15) / 16 * 16;
 
 // The argument blocks live in device memory (uniform fields become scalar
 // loads; no private copy of a by-value parameter is needed).
@@ -1406,10 +1408,12 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     extern __shared__ __align__(16) char smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
     // block: [network weights (learned)] then per wave [tree | network tiles | state]
-    MlpLds *mlpw = reinterpret_cast<MlpLds *>(smem);
+    LearnedLds *lrn = reinterpret_cast<LearnedLds *>(smem);
+    MlpLds *mlpw = &lrn->net;
     char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
     if (SK == kSkLearned) {
         stage_weights(mlpw, B.mlp);
+        for (int i = threadIdx.x; i < kEtabN; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
         __syncthreads();
     }
     const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)B.lds_state_bytes;
@@ -1437,7 +1441,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
         }
         const TrajArgs &a = B.mats[B.order[lo]];
         const Traj<OwnRC<SK>::value, DM, WT> T(a, state, tree);
-        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work, mlpw, mlps);
+        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work, lrn, mlps);
     }
     if (lane_id() == 0 && B.work_totals) {
         atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);

@@ -186,3 +186,28 @@ def test_learned_proposal_mean_within_ci():
     out = O.run(O.OMatrix(M), _learned(model), seed=3, count=20000, nthreads=8)
     st = O.stats(out["logw"], out["alive"])
     assert abs(math.exp(st["log_estimate"]) / per - 1) <= 4.5 * st["rse"]
+
+
+def _etab_exact(d):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    v = Decimal(16777216) * (Decimal(-d) / Decimal(16)).exp()
+    return int(v.to_integral_value(rounding="ROUND_HALF_EVEN")), v
+
+
+def test_softmax_table_is_rounding_stable_and_matches_the_oracle():
+    """E[d] = rint(2^24 exp(-d/16)): every entry sits at least 2e-9 (relative)
+    away from a rounding boundary, so any exp correct to 1e-12 -- the
+    oracle's and the device's -- yields the same integer table; the oracle's
+    integer weights for two candidates with logit gap d follow from it."""
+    for d in range(2048):
+        e, v = _etab_exact(d)
+        if v >= 0.5:
+            frac = v - int(v)
+            assert abs(float(frac) - 0.5) / float(v) > 1e-12
+    for d in (0, 1, 7, 16, 100, 333, 1000, 2047, 2048, 5000):
+        e = _etab_exact(d)[0] if d < 2048 else 0
+        w = O.learned_weights([0, -d], 0.0).astype(np.int64)
+        S = (1 << 24) + e
+        assert w[0] == max(1, round((1 << 24) * ((1 << 24) / S)))
+        assert w[1] == max(1, round((1 << 24) * (e / S)))

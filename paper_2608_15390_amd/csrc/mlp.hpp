@@ -97,27 +97,26 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
                                                  f32x4 z2[4], float logit[4]) {
     const int l = lane_id();
     const int c0 = l % 16, r0 = 4 * (l / 16);
+    // ReLU, and on the inference grid: snap to k/64, k in [0, 255] (one
+    // round and one median); such values are exact in bf16
     auto act = [](float z) -> float {
-        float h = z > 0.0f ? z : 0.0f;
-        if (QUANT) {
-            float k = rintf(h * 64.0f);
-            k = k > 255.0f ? 255.0f : k;
-            h = k * (1.0f / 64.0f);
-        }
-        return h;
+        if (QUANT) return __builtin_amdgcn_fmed3f(rintf(z * 64.0f), 0.0f, 255.0f) * (1.0f / 64.0f);
+        return z > 0.0f ? z : 0.0f;
     };
-    // layer 1: [16 x 16] x [16 x 64]
+    auto act_bf16 = [&](float z) -> short {
+        const float h = act(z);
+        return QUANT ? (short)(__float_as_uint(h) >> 16) : to_bf16(h);
+    };
+    // layer 1: [16 x 16] x [16 x 64], the bias as the accumulator's start
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         bf16x4 b = {0, 0, 0, 0};
         if (l < 32) b = *reinterpret_cast<const bf16x4 *>(&W->w1[(nt * 32 + l) * 4]);
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float bias = W->b1[16 * nt + c0];
+        f32x4 acc = {bias, bias, bias, bias};
         acc = mfma16(xa, b, acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[j] = acc[j] + W->b1[16 * nt + c0];
-            T->h[(r0 + j) * kH + 16 * nt + c0] = to_bf16(act(acc[j]));
-        }
+        for (int j = 0; j < 4; ++j) T->h[(r0 + j) * kH + 16 * nt + c0] = act_bf16(acc[j]);
         z1[nt] = acc;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -129,16 +128,20 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
     float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float bias = W->b2[16 * nt + c0];
+        f32x4 acc = {bias, bias, bias, bias};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&W->w2[((ks * 4 + nt) * 64 + l) * 4]);
             acc = mfma16(a2[ks], b, acc);
         }
+        const float w3 = W->w3[16 * nt + c0];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            acc[j] = acc[j] + W->b2[16 * nt + c0];
-            part[j] = part[j] + act(acc[j]) * W->w3[16 * nt + c0];
+            // on the grid every product and partial sum is exact, so a fused
+            // multiply-add rounds nothing
+            if (QUANT) part[j] = __builtin_fmaf(act(acc[j]), w3, part[j]);
+            else part[j] = part[j] + act(acc[j]) * w3;
         }
         z2[nt] = acc;
     }

@@ -576,6 +576,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     int64_t total = 0;
     uint64_t state_bytes = 0;
     int32_t tree_total = 0;
+    std::vector<uint64_t> mat_bytes(count, 0);
     for (size_t b = 0; b < count; ++b) {
         if ((rc = get_prepared(&h->mats[b], sched->initial_dm, sched->K0, s, &prep[b]))) return rc;
         total += parts[b].count;
@@ -613,6 +614,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         L.bytes = (uint32_t)((o + 255) / 256 * 256);
         if (o >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
         state_bytes = std::max<uint64_t>(state_bytes, L.bytes);
+        mat_bytes[b] = L.bytes;
 
         TrajArgs &a = h->args_host[b];
         a.A = DevMat{n, (int32_t)P->m, P->row_ptr, P->col_idx, P->col_ptr, P->row_idx, P->csc2csr,
@@ -678,7 +680,26 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     // ---- tier and launch shape
     const size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
     const size_t kLdsBlock = 64 * 1024, kLdsCU = 160 * 1024;
-    const bool lds = tree_bytes + state_bytes <= 32 * 1024 && !(h->opt_flags & PE_FLAG_FORCE_HBM);
+    // per-matrix tier: a matrix whose state fits beside the tree in 32 KB runs
+    // in LDS, unless such matrices carry under half of the launch's work (then
+    // reserving their LDS would only cost the others occupancy)
+    double work_lds = 0.0, work_all = 0.0;
+    uint64_t lds_cap = 0, hbm_cap = 0;
+    std::vector<int32_t> tier(count, 0);
+    for (size_t b = 0; b < count; ++b) {
+        const double wgt = (double)prep[b]->m * h->mats[b].n * (double)parts[b].count;
+        work_all += wgt;
+        if (tree_bytes + mat_bytes[b] <= 32 * 1024 && !(h->opt_flags & PE_FLAG_FORCE_HBM)) {
+            tier[b] = 1;
+            work_lds += wgt;
+        }
+    }
+    if (work_lds < 0.5 * work_all) std::fill(tier.begin(), tier.end(), 0);
+    for (size_t b = 0; b < count; ++b) {
+        if (tier[b]) lds_cap = std::max<uint64_t>(lds_cap, mat_bytes[b]);
+        else hbm_cap = std::max<uint64_t>(hbm_cap, mat_bytes[b]);
+        h->args_host[b].lds_tier = tier[b];
+    }
     static_assert(kMlpBlockBytes % 16 == 0 && kMlpWaveBytes % 16 == 0, "LDS carve-outs keep 16-byte alignment");
     BatchArgs &B = h->batch_host;
     B = BatchArgs{};
@@ -695,7 +716,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.etab = learned ? h->etab : nullptr;
     const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     int wpb = wpb_req > 0 ? wpb_req : 4;
-    size_t per_wave = tree_bytes + (size_t)B.lds_mlp_bytes + (lds ? state_bytes : 0);
+    size_t per_wave = tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
     wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
     const size_t shmem = block_fixed + (size_t)wpb * per_wave;
     if (shmem > kLdsBlock) return fail(PE_ENOTSUP, "per-trajectory LDS need exceeds one block's LDS");
@@ -716,11 +737,10 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     const unsigned blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((total + wpb - 1) / wpb, (int64_t)h->cu_count * (int64_t)per_cu));
     B.waves_per_block = wpb;
-    if (lds) {
-        B.hbm_state = nullptr;
-        B.lds_state_bytes = (int32_t)state_bytes;
-    } else {
-        const size_t need = (size_t)blocks * wpb * state_bytes;
+    B.lds_state_bytes = (int32_t)lds_cap;
+    B.hbm_state = nullptr;
+    if (hbm_cap > 0) {
+        const size_t need = (size_t)blocks * wpb * hbm_cap;
         if (h->hbm_bytes < need) {
             dfree(h->hbm_state);
             h->hbm_bytes = 0;
@@ -728,8 +748,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
             h->hbm_bytes = need;
         }
         B.hbm_state = h->hbm_state;
-        B.hbm_stride = state_bytes;
-        B.lds_state_bytes = 0;
+        B.hbm_stride = hbm_cap;
     }
 
     PE_HIP(hipMemcpyAsync(h->args_dev, h->args_host.data(), sizeof(TrajArgs) * count, hipMemcpyHostToDevice, s));

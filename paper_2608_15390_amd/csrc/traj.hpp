@@ -67,6 +67,7 @@ struct TrajArgs {
     TreeLayout tree;
     StateLayout st;
     int32_t ok0;               // 0: the input has no perfect matching
+    int32_t lds_tier;          // 1: this matrix's state lives in the wave's LDS slot
     int32_t vertex_rule, sk_policy, dm_policy, K;
     int32_t scaled;            // proposal uses r/c
     double theta_th, theta_tr;
@@ -1386,11 +1387,11 @@ struct BatchArgs {
     int64_t total;
     uint32_t *work_next;      // item counter (zeroed before launch)
     unsigned long long *work_totals;  // [6]: scanned, decrements, local entries, local values, sweeps, tiles
-    char *hbm_state;          // HBM tier: base of per-wave slots; nullptr = LDS tier
+    char *hbm_state;          // base of the per-wave HBM slots, or nullptr if every matrix is LDS tier
     uint64_t hbm_stride;
     int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
     int32_t lds_mlp_bytes;    // LDS bytes per wave for the network's tiles (learned)
-    int32_t lds_state_bytes;  // LDS tier: bytes of state per wave
+    int32_t lds_state_bytes;  // bytes of LDS state per wave (largest LDS-tier matrix), or 0
     int32_t waves_per_block;
     const float *mlp;         // learned proposal parameters (staged per block), or nullptr
     const int64_t *etab;      // learned proposal's softmax table (staged per block)
@@ -1420,13 +1421,11 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     char *mine = waves + (size_t)wave * per_wave;
     uint32_t *tree = reinterpret_cast<uint32_t *>(mine);
     TileLds *mlps = reinterpret_cast<TileLds *>(mine + B.lds_tree_bytes);
-    char *state;
-    if (B.hbm_state) {
-        const uint64_t slot = (uint64_t)blockIdx.x * B.waves_per_block + wave;
-        state = B.hbm_state + slot * B.hbm_stride;
-    } else {
-        state = mine + B.lds_tree_bytes + B.lds_mlp_bytes;
-    }
+    // per-matrix tier: the wave's LDS slot (sized for the largest LDS-tier
+    // matrix of the launch) or its HBM slot
+    char *lds_state = mine + B.lds_tree_bytes + B.lds_mlp_bytes;
+    char *hbm_state = B.hbm_state ? B.hbm_state + ((uint64_t)blockIdx.x * B.waves_per_block + wave) * B.hbm_stride
+                                  : nullptr;
     Work work;
     for (;;) {
         uint32_t q = 0;
@@ -1440,7 +1439,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
             if (B.item_off[mid] <= (int64_t)q) lo = mid; else hi = mid - 1;
         }
         const TrajArgs &a = B.mats[B.order[lo]];
-        const Traj<OwnRC<SK>::value, DM, WT> T(a, state, tree);
+        const Traj<OwnRC<SK>::value, DM, WT> T(a, a.lds_tier ? lds_state : hbm_state, tree);
         run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work, lrn, mlps);
     }
     if (lane_id() == 0 && B.work_totals) {

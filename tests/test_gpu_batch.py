@@ -140,3 +140,29 @@ def test_graph_replays_equal_eager_runs():
                 assert rg[f] == re_[f] or (math.isnan(rg[f]) and math.isnan(re_[f])), (rep, f)
         assert other["results"][0]["n_traj"] == 17
     bt.close()
+
+
+@pytest.mark.parametrize("name", ["local_nodm", "plain"])
+def test_mixed_tiers_in_one_launch(name):
+    """Small matrices run with their state in LDS and a large one in HBM
+    within the same launch; every matrix still equals the oracle."""
+    import paper_2608_15390_amd as P
+    mats = _small_batch(count=6, seed=21) + [G.planted_bernoulli(2500, 6.0 / 2500, 77, planted="random")]
+    counts = [400] * 6 + [2]
+    sched = P.preset(name)
+    print(f"[gpu] mixed tiers n={[M.n for M in mats]} sched={name}", flush=True)
+    bt = P.PermEstBatch(mats)
+    out = bt.run(counts, 13, sched, want_hash=True)
+    torch.cuda.synchronize()
+    lw = out["logw"].cpu().numpy()
+    al = out["alive"].cpu().numpy()
+    ph = out["path_hash"].cpu().numpy().view(np.uint64)
+    off = out["offsets"]
+    for b, M in enumerate(mats):
+        o = O.run(O.OMatrix(M), _osched(sched), seed=13, first=0, count=counts[b], b=b, nthreads=8)
+        sl = slice(off[b], off[b + 1])
+        np.testing.assert_array_equal(al[sl], o["alive"], err_msg=f"matrix {b}")
+        np.testing.assert_array_equal(ph[sl], o["path_hash"], err_msg=f"matrix {b}")
+        live = o["alive"] == 1
+        np.testing.assert_allclose(lw[sl][live], o["logw"][live], rtol=1e-12, atol=0)
+    bt.close()

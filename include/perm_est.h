@@ -76,6 +76,12 @@ typedef struct perm_est perm_est_t; /* opaque; owns all device state */
 #define PE_FLAG_FORCE_HBM 1u  /* keep per-trajectory state in HBM scratch even
                                  when it would fit in LDS (results are
                                  identical; used to cross-check the tiers) */
+#define PE_FLAG_WAVE_PER_TRAJECTORY 2u
+                              /* run every trajectory on a whole wave; by
+                                 default a single matrix in HBM scratch under
+                                 the plain or learned proposal (no inner SK or
+                                 DM, minimum degree) runs four trajectories per
+                                 wave.  Results are identical either way     */
 
 typedef struct {
     int32_t device;  /* HIP device ordinal                                 */

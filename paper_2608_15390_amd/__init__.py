@@ -61,7 +61,7 @@ class _ModelMixin:
 class PermEst(_ModelMixin):
     """One sparse matrix resident on one GPU."""
 
-    def __init__(self, M: SparseMatrix, device: int = 0, force_hbm: bool = False):
+    def __init__(self, M: SparseMatrix, device: int = 0, force_hbm: bool = False, wave_per_trajectory: bool = False):
         import torch  # noqa: F401  (initialises the HIP runtime the library shares)
 
         self._lib = N.load()
@@ -74,7 +74,8 @@ class PermEst(_ModelMixin):
         cp = np.ascontiguousarray(M.col_ptr, dtype=np.int32)
         ri = np.ascontiguousarray(M.row_idx, dtype=np.int32)
         val = None if M.val is None else np.ascontiguousarray(M.val, dtype=np.float32)
-        opts = N.Options(device, 1 if force_hbm else 0)
+        opts = N.Options(device, (N.PE_FLAG_FORCE_HBM if force_hbm else 0) |
+                         (N.PE_FLAG_WAVE_PER_TRAJECTORY if wave_per_trajectory else 0))
         N.check(self._lib.perm_est_create(
             self.n, self.m, rp.ctypes.data, ci.ctypes.data, cp.ctypes.data, ri.ctypes.data,
             None if val is None else val.ctypes.data, C.byref(opts), C.byref(self._h)))

@@ -95,6 +95,7 @@ EXPORTS = [
 ]
 
 PE_FLAG_FORCE_HBM = 1
+PE_FLAG_WAVE_PER_TRAJECTORY = 2
 PE_RUN_AUTOTUNE = 1
 PE_RUN_GRAPH = 2
 PE_SK_LEARNED = 4

@@ -17,6 +17,7 @@
 #include "perm_est.h"
 #include "prep.hpp"
 #include "reduce.hpp"
+#include "rows.hpp"
 
 using namespace pe;
 
@@ -437,6 +438,24 @@ const void *traj_kernel_fn(int sk, bool dm, bool wt) {
     }
 }
 
+// four-trajectories-per-wave kernel (plain scaled or learned proposal)
+const void *rows_kernel_fn(int sk, bool wt) {
+    if (sk == PE_SK_LEARNED)
+        return wt ? (const void *)&traj_rows_kernel<kSkLearned, true> : (const void *)&traj_rows_kernel<kSkLearned, false>;
+    return wt ? (const void *)&traj_rows_kernel<kSkNone, true> : (const void *)&traj_rows_kernel<kSkNone, false>;
+}
+
+void launch_rows(int sk, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+                 const BatchArgs *b) {
+    if (sk == PE_SK_LEARNED) {
+        if (wt) traj_rows_kernel<kSkLearned, true><<<blocks, threads, shmem, s>>>(b);
+        else traj_rows_kernel<kSkLearned, false><<<blocks, threads, shmem, s>>>(b);
+    } else {
+        if (wt) traj_rows_kernel<kSkNone, true><<<blocks, threads, shmem, s>>>(b);
+        else traj_rows_kernel<kSkNone, false><<<blocks, threads, shmem, s>>>(b);
+    }
+}
+
 // upper bound on resident trajectory waves per CU for the default launch shape
 #ifndef PE_MAX_WAVES_PER_CU
 #define PE_MAX_WAVES_PER_CU 32
@@ -499,7 +518,8 @@ int make_matrix(perm_est *h, int32_t n, int64_t nnz, const int32_t *row_ptr, con
 }
 
 int new_handle(const perm_est_options *opts, perm_est **out) {
-    if (opts && (opts->flags & ~PE_FLAG_FORCE_HBM) != 0) return fail(PE_EINVAL, "unknown option flags");
+    if (opts && (opts->flags & ~(PE_FLAG_FORCE_HBM | PE_FLAG_WAVE_PER_TRAJECTORY)) != 0)
+        return fail(PE_EINVAL, "unknown option flags");
     perm_est *h = new (std::nothrow) perm_est();
     if (!h) return fail(PE_ENOMEM, "host allocation failed");
     h->device = opts ? opts->device : 0;
@@ -714,9 +734,16 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.lds_mlp_bytes = learned ? kMlpWaveBytes : 0;
     B.mlp = learned ? h->mlp : nullptr;
     B.etab = learned ? h->etab : nullptr;
+    // four trajectories per wave (16-lane rows) for a single large matrix
+    // under the plain scaled or the learned proposal: short candidate lists
+    // leave most of a wave idle, so rows give 4x the parallelism per wave
+    const bool rows = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD &&
+                      (sched->sk_policy == PE_SK_NONE || learned) && hbm_cap > 0 && !parts[0].path &&
+                      !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY);
+    const int tpw = rows ? 4 : 1;  // trajectories per wave
     const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     int wpb = wpb_req > 0 ? wpb_req : 4;
-    size_t per_wave = tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
+    size_t per_wave = (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
     wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
     const size_t shmem = block_fixed + (size_t)wpb * per_wave;
     if (shmem > kLdsBlock) return fail(PE_ENOTSUP, "per-trajectory LDS need exceeds one block's LDS");
@@ -726,8 +753,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     } else {
         // as many resident blocks as registers and LDS allow, up to the cap
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, traj_kernel_fn(sched->sk_policy, dm, wt), wpb * kWave,
-                                                         shmem) != hipSuccess || nb < 1) {
+        const void *kfn = rows ? rows_kernel_fn(sched->sk_policy, wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, wpb * kWave, shmem) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = std::max(1, 16 / wpb);
         }
@@ -735,12 +762,12 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     }
     per_cu = std::max<size_t>(1, std::min<size_t>(per_cu, kLdsCU / std::max<size_t>(shmem, 1)));
     const unsigned blocks = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((total + wpb - 1) / wpb, (int64_t)h->cu_count * (int64_t)per_cu));
+        1, std::min<int64_t>((total + (int64_t)wpb * tpw - 1) / ((int64_t)wpb * tpw), (int64_t)h->cu_count * (int64_t)per_cu));
     B.waves_per_block = wpb;
     B.lds_state_bytes = (int32_t)lds_cap;
     B.hbm_state = nullptr;
     if (hbm_cap > 0) {
-        const size_t need = (size_t)blocks * wpb * hbm_cap;
+        const size_t need = (size_t)blocks * wpb * tpw * hbm_cap;
         if (h->hbm_bytes < need) {
             dfree(h->hbm_state);
             h->hbm_bytes = 0;
@@ -763,7 +790,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         k_set_u32<<<1, 1, 0, q>>>(h->work + 1, 0u);
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
-        launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
+        if (rows) launch_rows(sched->sk_policy, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
+        else launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
         PE_HIP(hipGetLastError());
         // per-matrix statistics over each matrix's slice of the outputs
         if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(h->seg_dev, h->stats);
@@ -771,7 +799,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         return PE_OK;
     };
     if (graph && !rec) {
-        const void *fn = traj_kernel_fn(sched->sk_policy, dm, wt);
+        const void *fn = rows ? rows_kernel_fn(sched->sk_policy, wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
         const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
                           h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
                           h->graph_res == (res != nullptr);

@@ -17,6 +17,9 @@ namespace pe {
 
 constexpr int kIn = 8, kH = 64;
 constexpr int kEtabN = 2048;  // entries of the integer softmax table (larger gaps weigh 0)
+// rint(2^24 exp(-d/16)) is 0 from d = 278 on, so the kernels keep only the
+// first kEtabLds entries of the table and read 0 beyond them
+constexpr int kEtabLds = 288;
 constexpr int kNParam = kIn * kH + kH + kH * kH + kH + kH + 1;  // 4801
 // offsets into the packed parameter vector
 constexpr int kOffW1 = 0, kOffB1 = kIn * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
@@ -50,11 +53,11 @@ struct MlpLds {
     float b3;
 };
 
-// The sampling side's LDS block: the network plus the integer softmax
-// table E[d] (values <= 2^24, so 32 bits hold them).
+// The sampling side's LDS block: the network plus the non-zero part of the
+// integer softmax table E[d] (values <= 2^24, so 32 bits hold them).
 struct LearnedLds {
     MlpLds net;
-    uint32_t etab[kEtabN];
+    uint32_t etab[kEtabLds];
 };
 
 // position of W2[r][c] in MlpLds::w2
@@ -92,6 +95,9 @@ struct TileLds {
 // z1[nt], z2[nt] (pre-activations, column 16 nt + l % 16, rows
 // 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (complete in the
 // last lane of each 16-lane group, l % 16 == 15).
+// four consecutive bf16 operands (8-byte aligned)
+__device__ __forceinline__ bf16x4 load_b4(const short *p) { return *reinterpret_cast<const bf16x4 *>(p); }
+
 template <bool QUANT>
 __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf16x4 xa, f32x4 z1[4],
                                                  f32x4 z2[4], float logit[4]) {
@@ -111,7 +117,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         bf16x4 b = {0, 0, 0, 0};
-        if (l < 32) b = *reinterpret_cast<const bf16x4 *>(&W->w1[(nt * 32 + l) * 4]);
+        if (l < 32) b = load_b4(&W->w1[(nt * 32 + l) * 4]);
         const float bias = W->b1[16 * nt + c0];
         f32x4 acc = {bias, bias, bias, bias};
         acc = mfma16(xa, b, acc);
@@ -132,7 +138,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         f32x4 acc = {bias, bias, bias, bias};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&W->w2[((ks * 4 + nt) * 64 + l) * 4]);
+            const bf16x4 b = load_b4(&W->w2[((ks * 4 + nt) * 64 + l) * 4]);
             acc = mfma16(a2[ks], b, acc);
         }
         const float w3 = W->w3[16 * nt + c0];

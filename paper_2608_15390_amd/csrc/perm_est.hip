@@ -438,22 +438,14 @@ const void *traj_kernel_fn(int sk, bool dm, bool wt) {
     }
 }
 
-// four-trajectories-per-wave kernel (plain scaled or learned proposal)
-const void *rows_kernel_fn(int sk, bool wt) {
-    if (sk == PE_SK_LEARNED)
-        return wt ? (const void *)&traj_rows_kernel<kSkLearned, true> : (const void *)&traj_rows_kernel<kSkLearned, false>;
-    return wt ? (const void *)&traj_rows_kernel<kSkNone, true> : (const void *)&traj_rows_kernel<kSkNone, false>;
+// four-trajectories-per-wave kernel (plain estimator)
+const void *rows_kernel_fn(bool wt) {
+    return wt ? (const void *)&traj_rows_kernel<true> : (const void *)&traj_rows_kernel<false>;
 }
 
-void launch_rows(int sk, bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
-                 const BatchArgs *b) {
-    if (sk == PE_SK_LEARNED) {
-        if (wt) traj_rows_kernel<kSkLearned, true><<<blocks, threads, shmem, s>>>(b);
-        else traj_rows_kernel<kSkLearned, false><<<blocks, threads, shmem, s>>>(b);
-    } else {
-        if (wt) traj_rows_kernel<kSkNone, true><<<blocks, threads, shmem, s>>>(b);
-        else traj_rows_kernel<kSkNone, false><<<blocks, threads, shmem, s>>>(b);
-    }
+void launch_rows(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s, const BatchArgs *b) {
+    if (wt) traj_rows_kernel<true><<<blocks, threads, shmem, s>>>(b);
+    else traj_rows_kernel<false><<<blocks, threads, shmem, s>>>(b);
 }
 
 // upper bound on resident trajectory waves per CU for the default launch shape
@@ -735,15 +727,32 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.mlp = learned ? h->mlp : nullptr;
     B.etab = learned ? h->etab : nullptr;
     // four trajectories per wave (16-lane rows) for a single large matrix
-    // under the plain scaled or the learned proposal: short candidate lists
-    // leave most of a wave idle, so rows give 4x the parallelism per wave
+    // under the plain estimator: short candidate lists leave most of a wave
+    // idle, so rows give 4x the parallelism per wave
     const bool rows = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD &&
-                      (sched->sk_policy == PE_SK_NONE || learned) && hbm_cap > 0 && !parts[0].path &&
+                      sched->sk_policy == PE_SK_NONE && hbm_cap > 0 && !parts[0].path &&
                       !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY);
     const int tpw = rows ? 4 : 1;  // trajectories per wave
     const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
-    int wpb = wpb_req > 0 ? wpb_req : 4;
     size_t per_wave = (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
+    int wpb = wpb_req > 0 ? wpb_req : 4;
+    if (rows && wpb_req <= 0) {
+        // the row kernel's LDS (four trees per wave) limits residency: take the
+        // block size that keeps the most waves resident per CU
+        int best = 0;
+        for (int w : {4, 2, 1}) {
+            const size_t sm = block_fixed + (size_t)w * per_wave;
+            if (sm > kLdsBlock) continue;
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rows_kernel_fn(wt), w * kWave, sm) !=
+                    hipSuccess) {
+                (void)hipGetLastError();
+                continue;
+            }
+            const int resident = std::min(nb * w, PE_MAX_WAVES_PER_CU);
+            if (resident > best) { best = resident; wpb = w; }
+        }
+    }
     wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
     const size_t shmem = block_fixed + (size_t)wpb * per_wave;
     if (shmem > kLdsBlock) return fail(PE_ENOTSUP, "per-trajectory LDS need exceeds one block's LDS");
@@ -753,7 +762,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     } else {
         // as many resident blocks as registers and LDS allow, up to the cap
         int nb = 0;
-        const void *kfn = rows ? rows_kernel_fn(sched->sk_policy, wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
+        const void *kfn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, wpb * kWave, shmem) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = std::max(1, 16 / wpb);
@@ -790,7 +799,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         k_set_u32<<<1, 1, 0, q>>>(h->work + 1, 0u);
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
-        if (rows) launch_rows(sched->sk_policy, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
+        if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
         else launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
         PE_HIP(hipGetLastError());
         // per-matrix statistics over each matrix's slice of the outputs
@@ -799,7 +808,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         return PE_OK;
     };
     if (graph && !rec) {
-        const void *fn = rows ? rows_kernel_fn(sched->sk_policy, wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
+        const void *fn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
         const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
                           h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
                           h->graph_res == (res != nullptr);

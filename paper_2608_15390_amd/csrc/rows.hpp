@@ -1,6 +1,6 @@
 // rows.hpp -- four trajectories per wave: each 16-lane row of a wave64 runs
-// its own trajectory of the plain scaled or the learned estimator (no
-// inner SK, no inner support filter, minimum-degree selection).
+// its own trajectory of the plain estimator (Alg. 2 with minimum-degree
+// selection, the outer scaling only: no inner SK, no inner support filter).
 //
 // Large sparse matrices give short candidate lists (the minimum-degree
 // vertex has a handful of neighbours; average lists hold ~8 entries), so a
@@ -8,9 +8,7 @@
 // on a chain of dependent memory accesses.  Rows let one instruction serve
 // four trajectories: four times the memory-level parallelism per wave and a
 // quarter of the instructions per trajectory step.  Row-wide reductions and
-// scans are DPP row shifts and row broadcasts; the learned proposal packs
-// four candidates of each row into one 16-record matrix-core tile, so a tile
-// serves all four trajectories.
+// scans are DPP row shifts and row broadcasts.
 //
 // Results are identical to traj_kernel's for the same (seed, trajectory,
 // matrix index): the step is the same sequence of integer decisions and
@@ -203,91 +201,6 @@ __device__ __forceinline__ uint32_t min16_skip(const uint4 &q0, const uint4 &q1,
 
 namespace pe {
 
-// The grid network of the learned proposal evaluated by one lane on the
-// vector ALU (weights from the block's LDS copy).  Every partial sum is an
-// exact float32 multiple of 2^-12, so the result equals the matrix-core
-// tile's.  Used for the rare candidates of lists longer than a row.
-__device__ int32_t valu_logit(const MlpLds *W, const float x[8]) {
-    float h1[kH];
-#pragma unroll 4
-    for (int c = 0; c < kH; ++c) {
-        float acc = W->b1[c];
-        for (int k = 0; k < kIn; ++k) {
-            const int idx = ((c >> 4) * 32 + 16 * (k >> 2) + (c & 15)) * 4 + (k & 3);
-            acc = __builtin_fmaf(x[k], from_bf16(W->w1[idx]), acc);
-        }
-        h1[c] = __builtin_amdgcn_fmed3f(rintf(acc * 64.0f), 0.0f, 255.0f) * (1.0f / 64.0f);
-    }
-    float out = W->b3;
-    for (int c = 0; c < kH; ++c) {
-        float acc = W->b2[c];
-        for (int k = 0; k < kH; ++k) acc = __builtin_fmaf(h1[k], from_bf16(W->w2[w2_index(k, c)]), acc);
-        const float h2 = __builtin_amdgcn_fmed3f(rintf(acc * 64.0f), 0.0f, 255.0f) * (1.0f / 64.0f);
-        out = __builtin_fmaf(h2, W->w3[c], out);
-    }
-    float L = rintf(out * 16.0f);
-    L = L < -1024.0f ? -1024.0f : (L > 1023.0f ? 1023.0f : L);
-    return (int32_t)L;
-}
-
-// Neighbourhood statistics (features x6, x7) of each lane's candidate u with
-// list [ub, ue): the row's candidate lists flattened over its 16 lanes.
-__device__ void row_candidate_stats(const RowTraj &T, bool cand, int32_t u, int32_t ub, int32_t ue, int32_t v,
-                                    uint64_t &s_u, int32_t &c2_u) {
-    const int rl = row_lane();
-    const bool u_row = u < T.n;
-    const int32_t len = cand ? ue - ub : 0;
-    int32_t total;
-    const int32_t off = row_excl_scan_i32(len, total);
-    s_u = 0;
-    c2_u = 0;
-    for (int32_t base = 0; base < total; base += kRowLanes) {
-        const int32_t f = base + rl;
-        const bool valid = f < total;
-        const int own = row_owner(valid ? f : total - 1, off);
-        const int32_t o_off = row_read(off, own);
-        const int32_t o_ub = row_read(ub, own);
-        const bool o_row = row_read((int)u_row, own) != 0;
-        uint32_t sv = 0, cv = 0;
-        if (valid) {
-            int32_t w;
-            float bv;
-            T.entry<false>(o_row, o_ub + (f - o_off), w, bv);
-            const uint32_t dw = T.deg[w];
-            if (dw != kRetired && dw != 0) {
-                sv = (1u << 20) / dw;
-                cv = (w != v && dw <= 2u) ? 1u : 0u;
-            }
-        }
-        auto seg = [&](uint32_t ys, uint32_t yc, uint32_t yo) {
-            if ((int)yo == own) { sv += ys; cv += yc; }
-        };
-        seg(dpp<kRowShr1>(0u, sv), dpp<kRowShr1>(0u, cv), dpp<kRowShr1>(~0u, (uint32_t)own));
-        seg(dpp<kRowShr2>(0u, sv), dpp<kRowShr2>(0u, cv), dpp<kRowShr2>(~0u, (uint32_t)own));
-        seg(dpp<kRowShr4>(0u, sv), dpp<kRowShr4>(0u, cv), dpp<kRowShr4>(~0u, (uint32_t)own));
-        seg(dpp<kRowShr8>(0u, sv), dpp<kRowShr8>(0u, cv), dpp<kRowShr8>(~0u, (uint32_t)own));
-        const int32_t lo_f = off > base ? off : base;
-        int32_t hi_f = off + len;
-        const int32_t cap = base + kRowLanes < total ? base + kRowLanes : total;
-        hi_f = hi_f < cap ? hi_f : cap;
-        const int src = hi_f > lo_f ? hi_f - 1 - base : 0;
-        const uint32_t seg_s = row_read(sv, src);
-        const uint32_t seg_c = row_read(cv, src);
-        if (hi_f > lo_f) { s_u += seg_s; c2_u += (int32_t)seg_c; }
-    }
-}
-
-// integer weight of one candidate from its logit (learned proposal)
-__device__ __forceinline__ uint64_t learned_weight(const uint32_t *etab, int32_t L, int32_t lmx, int64_t S,
-                                                   int32_t kc, double alpha) {
-    if (kc == 1) return 1ull;
-    const int32_t d = lmx - L;
-    const int64_t E = d < kEtabN ? (int64_t)etab[d] : 0;
-    const double qq = (1.0 - alpha) * (double)E / (double)S + alpha / (double)kc;
-    const double rr = rint(16777216.0 * qq);
-    return rr >= 1.0 ? (uint64_t)rr : 1ull;
-}
-
 // scaled proposal weight of one candidate (Eq. q, integerised)
 __device__ __forceinline__ uint64_t scaled_weight(float s, float smax, bool uniform, int32_t kc) {
     if (kc == 1 || uniform) return 1ull;
@@ -295,27 +208,18 @@ __device__ __forceinline__ uint64_t scaled_weight(float s, float smax, bool unif
     return rr >= 1.0f ? (uint64_t)rr : 1ull;
 }
 
-template <int SK, bool WT>
+// the plain estimator (Alg. 2 with minimum degree, outer scaling only),
+// four trajectories per wave; WT: weighted entries
+template <bool WT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 traj_rows_kernel(const BatchArgs *__restrict__ bp) {
-    constexpr bool LEARNED = SK == kSkLearned;
     const BatchArgs &B = *bp;
     const TrajArgs &a = B.mats[0];
     extern __shared__ __align__(16) char smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    LearnedLds *lrn = reinterpret_cast<LearnedLds *>(smem);
-    char *waves = smem + (LEARNED ? kMlpBlockBytes : 0);
-    if (LEARNED) {
-        stage_weights(&lrn->net, B.mlp);
-        for (int i = threadIdx.x; i < kEtabN; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
-        __syncthreads();
-    }
-    const MlpLds *W = &lrn->net;
-    const uint32_t *etab = lrn->etab;
-    const int l = lane_id(), r = row_id(), rl = row_lane();
+    const int r = row_id(), rl = row_lane();
     const int32_t n = a.A.n;
-    char *mine = waves + (size_t)wave * (4 * (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes);
-    TileLds *tile = reinterpret_cast<TileLds *>(mine + 4 * (size_t)B.lds_tree_bytes);
+    char *mine = smem + (size_t)wave * 4 * (size_t)B.lds_tree_bytes;
     char *state = B.hbm_state + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
     const StateLayout &L = a.st;
     const RowTraj T{a, reinterpret_cast<uint16_t *>(state + L.deg), reinterpret_cast<int32_t *>(state + L.lst_a),
@@ -359,165 +263,85 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
         }
         if (!ballot(phase != 2)) break;
         const bool run = phase == 1 && alive && t < n;
-
-        // ---- block 1: select v, read its candidates, learned features
-        int32_t v = -1, gsel = -1, vb = 0, ve = 0;
-        uint4 lq0 = make_uint4(0, 0, 0, 0), lq1 = lq0;  // this lane's 16 leaves of v's group
-        bool fast_v = false, cand = false, need_net = false;
-        int32_t cy = -1, cub = 0, cue = 0, kc = 0;
-        uint32_t cd = 0;
-        float bv = 0.0f;
-        float x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool finished = phase == 1 && !run;  // completed or dead at the previous step
         if (run) {
-            // minimum-degree selection down the row's min-tree, then the leaf group
-            const int top = a.tree.levels - 1;
-            const uint32_t m = T.global_min();
-            int32_t g = 0;
-            for (int kk = top; kk >= 0; --kk) {
-                // first node of the block [64 g, 64 g + 64) of level kk holding m
-                const int32_t base = 64 * g + 4 * rl;
-                int j = 4;
+            // ---- minimum-degree selection down the row's min-tree, then the leaf group
+            int32_t v = -1, gsel = -1;
+            uint4 lq0 = make_uint4(0, 0, 0, 0), lq1 = lq0;  // this lane's 16 leaves of v's group
+            {
+                const int top = a.tree.levels - 1;
+                const uint32_t m = T.global_min();
+                int32_t g = 0;
+                for (int kk = top; kk >= 0 && g >= 0; --kk) {
+                    // first node of the block [64 g, 64 g + 64) of level kk holding m
+                    const int32_t base = 64 * g + 4 * rl;
+                    int j = 4;
 #pragma unroll
-                for (int i = 3; i >= 0; --i)
-                    if (base + i < a.tree.size[kk] && T.level(kk)[base + i] == m) j = i;
-                const uint32_t bits = row_bits(ballot(j < 4));
-                const int src = __ffs(bits) - 1;
-                const int js = row_read(j, src < 0 ? 0 : src);
-                g = 64 * g + 4 * src + js;
-                if (bits == 0) g = -1;
-                if (g < 0) break;
-            }
-            if (g >= 0) {
-                T.load_leaves(g, lq0, lq1);
-                const int j = first16(lq0, lq1, m);
-                const uint32_t bits = row_bits(ballot(j < 16));
-                const int src = __ffs(bits) - 1;
-                const int js = row_read(j, src < 0 ? 0 : src);
-                if (bits) {
-                    v = 256 * g + 16 * src + js;
-                    gsel = g;
+                    for (int i = 3; i >= 0; --i)
+                        if (base + i < a.tree.size[kk] && T.level(kk)[base + i] == m) j = i;
+                    const uint32_t bits = row_bits(ballot(j < 4));
+                    const int src = __ffs(bits) - 1;
+                    const int js = row_read(j, src < 0 ? 0 : src);
+                    g = bits ? 64 * g + 4 * src + js : -1;
+                }
+                if (g >= 0) {
+                    T.load_leaves(g, lq0, lq1);
+                    const int j = first16(lq0, lq1, m);
+                    const uint32_t bits = row_bits(ballot(j < 16));
+                    const int src = __ffs(bits) - 1;
+                    const int js = row_read(j, src < 0 ? 0 : src);
+                    if (bits) {
+                        v = 256 * g + 16 * src + js;
+                        gsel = g;
+                    }
                 }
             }
+            bool dead = false;
             if (v < 0 || v >= 2 * n) {  // internal inconsistency: report, never index
                 if (rl == 0) atomicOr(a.err, 1u);
-                alive = false;
+                dead = true;
             }
-        }
-        const bool step_ok = run && alive;
-        const bool v_row = v < n;
-        if (step_ok) {
-            T.list(v, vb, ve);
-            fast_v = ve - vb <= kRowLanes;
-            if (fast_v) {
+            int32_t u = -1, kc = 0, vb = 0, ve = 0, cy = -1;
+            uint32_t cd = 0, d_u = 0;
+            bool cand = false, fast_v = false;
+            float b_vu = 1.0f;
+            uint64_t Wt = 0, w_u = 1;
+            const bool v_row = v < n;
+            if (!dead) {
+                T.list(v, vb, ve);
+                fast_v = ve - vb <= kRowLanes;
+            }
+            // ---- candidates, proposal of Eq. (q) (outer scaling), draw
+            if (!dead && fast_v) {
                 const int32_t p = vb + rl;
+                float bv = 0.0f;
                 if (p < ve) {
                     T.entry<WT>(v_row, p, cy, bv);
                     cd = T.deg[cy];
-                    if (LEARNED) T.list(cy, cub, cue);
                     cand = cd != kRetired;
                 }
                 kc = __popc(row_bits(ballot(cand)));
-                if (LEARNED && kc > 1) {
-                    uint64_t su;
-                    int32_t c2;
-                    row_candidate_stats(T, cand, cy, cub, cue, v, su, c2);
-                    const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
-                    const float r0r = a.r0 ? a.r0[cand ? rho_c : 0] : 1.0f;
-                    const float c0g = a.c0 ? a.c0[cand ? gam_c - n : 0] : 1.0f;
-                    learned_features(x, v_row ? (uint32_t)kc : cd, v_row ? cd : (uint32_t)kc, r0r, c0g, t, n, v_row,
-                                     su, c2);
-                    if (!cand) {
-#pragma unroll
-                        for (int f = 0; f < 8; ++f) x[f] = 0.0f;
-                    }
-                    need_net = true;
-                }
-            }
-        }
-
-        // ---- block 2 (whole wave): network tiles, four candidates of each row per tile
-        int32_t Lg = 0;
-        if (LEARNED) {
-            // tiles: enough to cover the longest candidate list among the rows
-            const int need_tiles = need_net ? (ve - vb + 3) / 4 : 0;
-            int ntiles = __builtin_amdgcn_readlane(need_tiles, 0);
-#pragma unroll
-            for (int rr = 1; rr < 4; ++rr) {
-                const int c = __builtin_amdgcn_readlane(need_tiles, 16 * rr);
-                ntiles = c > ntiles ? c : ntiles;
-            }
-            const int grp = l >> 4;
-            for (int tau = 0; tau < ntiles; ++tau) {
-                // record i = l % 16 of the tile: row i / 4, candidate lane 4 tau + i % 4 of that row
-                const int i = l & 15;
-                const int src = 16 * (i >> 2) + 4 * tau + (i & 3);
-                bf16x4 xa;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float lo = __shfl(x[j], src), hi = __shfl(x[4 + j], src);
-                    xa[j] = grp == 0 ? (short)(__float_as_uint(lo) >> 16)
-                                     : (grp == 1 ? (short)(__float_as_uint(hi) >> 16) : (short)0);
-                }
-                f32x4 z1[4], z2[4];
-                float lg[4];
-                mlp_tile_forward<true>(W, tile, xa, z1, z2, lg);
-                // row r's candidates 4 tau .. 4 tau + 3 sit in lane 16 r + 15, registers 0..3
-                const float y0 = row_bcast_f<15>(lg[0]), y1 = row_bcast_f<15>(lg[1]);
-                const float y2 = row_bcast_f<15>(lg[2]), y3 = row_bcast_f<15>(lg[3]);
-                const int js = rl - 4 * tau;
-                if (js >= 0 && js < 4) {
-                    const float y = js == 0 ? y0 : (js == 1 ? y1 : (js == 2 ? y2 : y3));
-                    float Lf = rintf(y * 16.0f);
-                    Lf = Lf < -1024.0f ? -1024.0f : (Lf > 1023.0f ? 1023.0f : Lf);
-                    Lg = (int32_t)Lf;
-                }
-            }
-            if (l == 0) work.mlp_tiles += (uint64_t)ntiles;
-        }
-
-        // ---- block 3: proposal weights, draw, weight update, removal, min-tree
-        bool finished = phase == 1 && !run;  // a completed or dead trajectory from the last step
-        if (step_ok) {
-            int32_t u = -1;
-            float b_vu = 1.0f;
-            uint64_t Wt = 0, w_u = 1;
-            uint32_t d_u = 0;
-            int u_lane = -1;
-            bool dead = false;
-            if (fast_v) {
                 if (kc == 0) {
                     dead = true;
                 } else {
-                    uint64_t w = 0;
-                    if (LEARNED) {
-                        const int32_t lmx = row_max_i32(cand ? Lg : -2147483647);
-                        const int32_t d = lmx - Lg;
-                        const int64_t E = (cand && d < kEtabN) ? (int64_t)etab[d] : 0;
-                        const int64_t S = (int64_t)row_sum_u64((uint64_t)E);
-                        if (cand) w = learned_weight(etab, Lg, lmx, S, kc, a.mix_alpha);
-                    } else {
-                        const float s = a.scaled ? bv * T.scale0(cy) : bv;
-                        const float smax = row_max_f32((cand && s > 0.0f) ? s : 0.0f);
-                        const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
-                        if (cand) w = scaled_weight(s, smax, uniform, kc);
-                    }
+                    const float s = a.scaled ? bv * T.scale0(cy) : bv;
+                    const float smax = row_max_f32((cand && s > 0.0f) ? s : 0.0f);
+                    const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
+                    const uint64_t w = cand ? scaled_weight(s, smax, uniform, kc) : 0ull;
                     const uint64_t incl = row_incl_scan_u64(w);
                     Wt = row_bcast64<15>(incl);
                     const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), Wt, a.seed, k,
                                                             a.b, (uint32_t)t)
                                               : 0ull;
                     const uint32_t hm = row_bits(ballot(w != 0 && incl > j && incl - w <= j));
-                    const int src = __ffs(hm) - 1;
-                    const int ss = src < 0 ? 0 : src;
-                    u = row_read(cy, ss);
-                    b_vu = row_read(bv, ss);
-                    w_u = row_read(w, ss);
-                    d_u = row_read(cd, ss);
-                    u_lane = ss;
-                    if (hm == 0) u = -1;
+                    const int src = hm ? __ffs(hm) - 1 : 0;
+                    u = hm ? row_read(cy, src) : -1;
+                    b_vu = row_read(bv, src);
+                    w_u = row_read(w, src);
+                    d_u = row_read(cd, src);
                     if (kc == 1) Wt = w_u;
                 }
-            } else {
+            } else if (!dead) {
                 // long list: candidates into lst_a, weights in passes of 16
                 float lmaxf = 0.0f;
                 for (int32_t base = vb; base < ve; base += kRowLanes) {
@@ -532,10 +356,8 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                     const uint32_t msk = row_bits(ballot(c0));
                     if (c0) {
                         T.lst_a[kc + __popc(msk & ((1u << rl) - 1u))] = y;
-                        if (!LEARNED) {
-                            const float s = a.scaled ? bvv * T.scale0(y) : bvv;
-                            lmaxf = s > lmaxf ? s : lmaxf;
-                        }
+                        const float s = a.scaled ? bvv * T.scale0(y) : bvv;
+                        lmaxf = s > lmaxf ? s : lmaxf;
                     }
                     kc += __popc(msk);
                 }
@@ -543,93 +365,37 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 if (kc == 0) {
                     dead = true;
                 } else {
-                    const float smax = LEARNED ? 0.0f : row_max_f32(lmaxf);
+                    const float smax = row_max_f32(lmaxf);
                     const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
-                    int32_t lmx = -2147483647;
-                    int64_t Ssum = 0;
-                    if (LEARNED && kc > 1) {
-                        // logits on the vector ALU into lst_b
-                        int32_t idx0 = 0;
-                        for (int32_t base = vb; base < ve; base += kRowLanes) {
-                            const int32_t p = base + rl;
-                            bool c0 = false;
-                            int32_t y = 0;
-                            float bvv = 0.0f;
-                            uint32_t dy = 0;
-                            int32_t yb = 0, ye = 0;
-                            if (p < ve) {
-                                T.entry<WT>(v_row, p, y, bvv);
-                                dy = T.deg[y];
-                                c0 = dy != kRetired;
-                                if (c0) T.list(y, yb, ye);
-                            }
-                            uint64_t su;
-                            int32_t c2;
-                            row_candidate_stats(T, c0, y, yb, ye, v, su, c2);
-                            const int32_t rho_c = v_row ? v : y, gam_c = v_row ? y : v;
-                            const float r0r = a.r0 ? a.r0[c0 ? rho_c : 0] : 1.0f;
-                            const float c0g = a.c0 ? a.c0[c0 ? gam_c - n : 0] : 1.0f;
-                            float xf[8];
-                            learned_features(xf, v_row ? (uint32_t)kc : dy, v_row ? dy : (uint32_t)kc, r0r, c0g, t,
-                                             n, v_row, su, c2);
-                            int32_t Ly = 0;
-                            if (c0) Ly = valu_logit(W, xf);
-                            const uint32_t msk = row_bits(ballot(c0));
-                            if (c0) {
-                                T.lst_b[idx0 + __popc(msk & ((1u << rl) - 1u))] = Ly;
-                                lmx = Ly > lmx ? Ly : lmx;
-                            }
-                            idx0 += __popc(msk);
-                        }
-                        lmx = row_max_i32(lmx);
-                        wave_fence();
-                        uint64_t part = 0;
-                        for (int32_t idx = rl; idx < kc; idx += kRowLanes) {
-                            const int32_t d = lmx - T.lst_b[idx];
-                            part += d < kEtabN ? (uint64_t)etab[d] : 0ull;
-                        }
-                        Ssum = (int64_t)row_sum_u64(part);
-                    }
-                    auto weight_of = [&](int32_t y, float bvv, int32_t ci) -> uint64_t {
-                        if (LEARNED) return learned_weight(etab, T.lst_b[ci], lmx, Ssum, kc, a.mix_alpha);
+                    auto weight_of = [&](int32_t y, float bvv) -> uint64_t {
                         const float s = a.scaled ? bvv * T.scale0(y) : bvv;
                         return scaled_weight(s, smax, uniform, kc);
                     };
-                    int32_t cbase = 0;
                     for (int32_t base = vb; base < ve; base += kRowLanes) {
                         const int32_t p = base + rl;
                         uint64_t w = 0;
-                        bool c0 = false;
                         int32_t y = 0;
                         float bvv = 0.0f;
                         if (p < ve) {
                             T.entry<WT>(v_row, p, y, bvv);
-                            c0 = T.deg[y] != kRetired;
+                            if (T.deg[y] != kRetired) w = weight_of(y, bvv);
                         }
-                        const uint32_t msk = row_bits(ballot(c0));
-                        if (c0) w = weight_of(y, bvv, cbase + __popc(msk & ((1u << rl) - 1u)));
-                        cbase += __popc(msk);
                         Wt += row_sum_u64(w);
                     }
                     const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), Wt, a.seed, k,
                                                             a.b, (uint32_t)t)
                                               : 0ull;
                     uint64_t pre = 0;
-                    cbase = 0;
                     bool found = false;
                     for (int32_t base = vb; base < ve && !found; base += kRowLanes) {
                         const int32_t p = base + rl;
                         uint64_t w = 0;
                         int32_t y = 0;
                         float bvv = 0.0f;
-                        bool c0 = false;
                         if (p < ve) {
                             T.entry<WT>(v_row, p, y, bvv);
-                            c0 = T.deg[y] != kRetired;
+                            if (T.deg[y] != kRetired) w = weight_of(y, bvv);
                         }
-                        const uint32_t msk = row_bits(ballot(c0));
-                        if (c0) w = weight_of(y, bvv, cbase + __popc(msk & ((1u << rl) - 1u)));
-                        cbase += __popc(msk);
                         const uint64_t incl = row_incl_scan_u64(w) + pre;
                         const uint32_t hm = row_bits(ballot(w != 0 && incl > j && incl - w <= j));
                         if (hm) {
@@ -663,12 +429,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
 
                 // N_t(u) \ {v}
                 int32_t ub, ue;
-                if (LEARNED && fast_v && u_lane >= 0) {
-                    ub = row_read(cub, u_lane);
-                    ue = row_read(cue, u_lane);
-                } else {
-                    T.list(u, ub, ue);
-                }
+                T.list(u, ub, ue);
                 const bool fast_u = ue - ub <= kRowLanes;
                 const bool u_row = u < n;
                 int32_t by = -1;
@@ -787,7 +548,6 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
     if (rl == 0 && B.work_totals) {
         atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);
         atomicAdd(B.work_totals + 1, (unsigned long long)work.dec);
-        atomicAdd(B.work_totals + 5, (unsigned long long)work.mlp_tiles);
     }
 }
 

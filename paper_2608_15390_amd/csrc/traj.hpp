@@ -951,7 +951,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 int64_t E = 0;
                 if (cand) {
                     const int32_t d = lmx - L;
-                    E = d < kEtabN ? (int64_t)etab[d] : 0;
+                    E = d < kEtabLds ? (int64_t)etab[d] : 0;
                 }
                 const int64_t S = (int64_t)wave_sum_u64((uint64_t)E);
                 if (cand) {
@@ -1099,7 +1099,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 uint64_t part = 0;
                 for (int32_t idx = l; idx < kc; idx += kWave) {
                     const int32_t d = lmx - T.lst_b[idx];
-                    part += d < kEtabN ? (uint64_t)etab[d] : 0ull;
+                    part += d < kEtabLds ? (uint64_t)etab[d] : 0ull;
                 }
                 Ssum = (int64_t)wave_sum_u64(part);
             }
@@ -1108,7 +1108,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 if (SK == kSkLearned) {
                     if (kc == 1) return 1ull;
                     const int32_t d = lmx - T.lst_b[ci];
-                    const int64_t E = d < kEtabN ? (int64_t)etab[d] : 0;
+                    const int64_t E = d < kEtabLds ? (int64_t)etab[d] : 0;
                     const double qq = (1.0 - a.mix_alpha) * (double)E / (double)Ssum + a.mix_alpha / (double)kc;
                     const double rr = rint(16777216.0 * qq);
                     return rr >= 1.0 ? (uint64_t)rr : 1ull;
@@ -1414,7 +1414,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
     if (SK == kSkLearned) {
         stage_weights(mlpw, B.mlp);
-        for (int i = threadIdx.x; i < kEtabN; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
+        for (int i = threadIdx.x; i < kEtabLds; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
         __syncthreads();
     }
     const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)B.lds_state_bytes;

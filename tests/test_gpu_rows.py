@@ -1,13 +1,12 @@
 """Four trajectories per wave (16-lane rows) for a single matrix in HBM
-scratch under the plain or the learned proposal: every trajectory equals the
-whole-wave kernel's and the oracle's, bit for bit, including lists longer
-than a row, weighted entries and dead ends."""
+scratch under the plain estimator (with or without the outer scaling):
+every trajectory equals the whole-wave kernel's and the oracle's, bit for
+bit, including lists longer than a row, weighted entries and dead ends."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
-from oracle import mlp as R
 from oracle import oracle as O
 from paper_2608_15390_amd import inputs as G
 
@@ -31,11 +30,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", [c[0] for c in CASES])
-@pytest.mark.parametrize("name", ["plain", "learned", "plain_outer"])
+@pytest.mark.parametrize("name", ["plain", "plain_outer"])
 def test_rows_match_whole_waves_and_oracle(case, name):
     import paper_2608_15390_amd as P
     M = dict(CASES)[case]()
-    model = R.quantize(R.init(41, scale=1.5))
     if name == "plain_outer":
         sched = P.preset("plain", initial_dm=1, K0=100)
     else:
@@ -45,8 +43,6 @@ def test_rows_match_whole_waves_and_oracle(case, name):
     outs = []
     for wave_per_traj in (False, True):
         h = P.PermEst(M, force_hbm=True, wave_per_trajectory=wave_per_traj)
-        if name == "learned":
-            h.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), 0.02)
         outs.append(h.run(5, count, 17, sched, want_hash=True, want_counters=True))
         torch.cuda.synchronize()
         h.close()
@@ -57,8 +53,7 @@ def test_rows_match_whole_waves_and_oracle(case, name):
     for f in ("log_estimate", "p_match", "ess", "n_alive", "n_steps", "n_entries_scanned", "n_decrements"):
         a, b = rows["result"][f], whole["result"][f]
         assert a == b or (a != a and b != b), f
-    o = O.run(O.OMatrix(M), _osched(sched, model if name == "learned" else None, 0.02), seed=17, first=5,
-              count=count, nthreads=8)
+    o = O.run(O.OMatrix(M), _osched(sched), seed=17, first=5, count=count, nthreads=8)
     al = rows["alive"].cpu().numpy()
     np.testing.assert_array_equal(al, o["alive"])
     np.testing.assert_array_equal(rows["path_hash"].cpu().numpy().view(np.uint64), o["path_hash"])
@@ -66,32 +61,29 @@ def test_rows_match_whole_waves_and_oracle(case, name):
     np.testing.assert_allclose(rows["logw"].cpu().numpy()[live], o["logw"][live], rtol=1e-12, atol=0)
 
 
-def test_rows_large_learned_sampled():
-    """n = 1e5 (the large workload) with the learned proposal: sampled ids
+def test_rows_large_sampled():
+    """n = 1e5 (the large workload), outer-scaled plain estimator: sampled ids
     against the oracle, and the whole-wave kernel on the same ids."""
     import paper_2608_15390_amd as P
     M = G.config_large(1)
-    model = R.quantize(R.init(43, scale=1.5))
-    sched = P.preset("learned")
+    sched = P.preset("plain", initial_dm=1, K0=100)
     h = P.PermEst(M)
-    h.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), 0.01)
-    out = h.run(0, 2048, 3, sched, want_hash=True)
+    out = h.run(0, 4096, 3, sched, want_hash=True)
     torch.cuda.synchronize()
     h.close()
     w = P.PermEst(M, wave_per_trajectory=True)
-    w.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), 0.01)
-    ref = w.run(0, 2048, 3, sched, want_hash=True)
+    ref = w.run(0, 4096, 3, sched, want_hash=True)
     torch.cuda.synchronize()
     w.close()
     for key in ("logw", "alive", "path_hash"):
         assert torch.equal(out[key], ref[key]), key
     A = O.OMatrix(M)
-    osch = _osched(sched, model, 0.01)
+    osch = _osched(sched)
     pre = O.prep(A, osch)
     lw = out["logw"].cpu().numpy()
     al = out["alive"].cpu().numpy()
     ph = out["path_hash"].cpu().numpy().view(np.uint64)
-    for kk in (0, 777, 2047):
+    for kk in (0, 777, 4095):
         o = O.run(A, osch, seed=3, first=kk, count=1, pre=pre)
         assert al[kk] == o["alive"][0] and ph[kk] == o["path_hash"][0], kk
         if o["alive"][0]:

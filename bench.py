@@ -32,6 +32,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -107,7 +109,6 @@ def chunked_run(est, first, n_traj, seed, sched, chunk):
     (results are identical per id), printing progress between launches.
     The batch statistics are recomputed from the per-trajectory ln X in FP64
     on the host: S1 = sum X, S2 = sum X^2 by log-sum-exp, ESS = S1^2 / S2."""
-    import numpy as np
     import torch
 
     lws, als, secs, done, steps = [], [], 0.0, 0, 0
@@ -137,6 +138,7 @@ def chunked_run(est, first, n_traj, seed, sched, chunk):
         rel_var = max(0.0, math.exp(ls2 - 2 * ls1) * n_traj - 1.0) * n_traj / max(n_traj - 1, 1)
         r["rse"] = math.sqrt(rel_var / n_traj)
         r["var_logw"] = float(np.var(x, ddof=1)) if x.size > 1 else 0.0
+    r["time_to_rse"] = time_to_rse(lw, al, secs)
     return r, secs
 
 
@@ -146,9 +148,49 @@ def summary(r, secs):
             "log_estimate": r["log_estimate"], "steps_per_traj": r["n_steps"] / r["n_traj"]}
 
 
-def ladder(params, plain_sched, learned_sched, seed):
+def prefix_rse(lw, al, m):
+    """RSE of the estimate from the first m trajectories (zeros included)."""
+    x = lw[:m][al[:m]]
+    if x.size == 0 or m < 2:
+        return math.inf
+    top = x.max()
+    ls1 = top + math.log(np.exp(x - top).sum())
+    ls2 = 2 * top + math.log(np.exp(2 * (x - top)).sum())
+    cv2 = m * (m * math.exp(ls2 - 2 * ls1) - 1.0) / (m - 1)
+    return math.sqrt(max(cv2, 0.0) / m)
+
+
+def time_to_rse(lw, al, secs, eps_list=(1e-1, 1e-2)):
+    """Time to a target RSE: checkpoints after 2^k trajectories and at the
+    end; the target counts as reached at the first checkpoint after the last
+    one that misses it, and never if the last one misses it.  Every
+    trajectory of a launch runs concurrently and costs about the same, so the
+    time of a checkpoint is the launch time pro rata."""
+    M = lw.size
+    cps = [1 << k for k in range(1, 64) if (1 << k) < M] + [M]
+    rses = [prefix_rse(lw, al, c) for c in cps]
+    out = {}
+    for eps in eps_list:
+        bad = [i for i, r in enumerate(rses) if not r <= eps]
+        if bad and bad[-1] == len(cps) - 1:
+            out[f"{eps:g}"] = None
+        else:
+            c = cps[bad[-1] + 1] if bad else cps[0]
+            out[f"{eps:g}"] = {"seconds": secs * c / M, "trajectories": c}
+    return out
+
+
+def bootstrap_ci(vals, reps=2000, seed=0):
+    """95 % percentile bootstrap interval of the mean over replicates."""
+    v = np.asarray(vals, dtype=np.float64)
+    g = np.random.default_rng(seed)
+    means = v[g.integers(0, v.size, size=(reps, v.size))].mean(axis=1)
+    return [float(np.percentile(means, 2.5)), float(np.percentile(means, 97.5))]
+
+
+def ladder(params, plain_sched, learned_sched, seeds):
     """The same comparison on smaller matrices of the same family, where the
-    effective sample size does not collapse."""
+    effective sample size does not collapse, replicated over run seeds."""
     import paper_2608_15390_amd as P
     from paper_2608_15390_amd import inputs as G
     from paper_2608_15390_amd import learned as LR
@@ -158,15 +200,59 @@ def ladder(params, plain_sched, learned_sched, seed):
         M = G.planted_uniform(n, 7 * n, 5)
         est = P.PermEst(M)
         est.set_model(params, LR.MIX_ALPHA)
-        row = {"n": n, "n_traj": cnt}
-        for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
-            est.run(0, 64, seed, sch, want_logw=False, want_alive=False)
-            out, secs = timed_run(est, 0, cnt, seed, sch)
-            row[name] = summary(out["result"], secs)
-        row["ratio"] = row["learned"]["ess_per_s"] / row["plain"]["ess_per_s"]
+        row = {"n": n, "n_traj": cnt, "seeds": list(seeds), "learned": [], "plain": [], "ratio": []}
+        for s in seeds:
+            for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
+                est.run(0, 64, s, sch, want_logw=False, want_alive=False)
+                out, secs = timed_run(est, 0, cnt, s, sch, want=True)
+                rec = summary(out["result"], secs)
+                rec["time_to_rse"] = time_to_rse(out["logw"].cpu().numpy(),
+                                                 out["alive"].cpu().numpy().astype(bool), secs)
+                row[name].append(rec)
+            row["ratio"].append(row["learned"][-1]["ess_per_s"] / row["plain"][-1]["ess_per_s"])
+        print(f"[bench]   ladder n={n}: ratios {[round(r, 3) for r in row['ratio']]}", file=sys.stderr, flush=True)
+        row["ratio_mean"] = float(np.mean(row["ratio"]))
+        row["ratio_ci95"] = bootstrap_ci(row["ratio"])
+        for name in ("learned", "plain"):
+            row[f"{name}_ess_per_s_mean"] = float(np.mean([r["ess_per_s"] for r in row[name]]))
+            row[f"{name}_var_logw_mean"] = float(np.mean([r["var_logw"] for r in row[name]]))
         rows.append(row)
         est.close()
     return rows
+
+
+def band_study(params, plain_sched, learned_sched, seed, cnt):
+    """Both methods on the n = 1e5 band matrix of mean degree 8 whose
+    permanent is known exactly (stored reference, dynamic program over the
+    band): the true relative error of each estimate."""
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+    from paper_2608_15390_amd import learned as LR
+
+    with open(os.path.join(ROOT, "tests", "golden", "band_n1e5_hw4.json")) as f:
+        ref = json.load(f)
+    M, _ = G.config_band(1)
+    h = hashlib.sha256()
+    for a in (M.row_ptr, M.col_idx, M.col_ptr, M.row_idx):
+        h.update(a.astype("<i4").tobytes())
+    if h.hexdigest() != ref["index_sha256"]:
+        return {"error": "the generator no longer builds the stored band matrix"}
+    lp = ref["log_permanent"]
+    est = P.PermEst(M)
+    est.set_model(params, LR.MIX_ALPHA)
+    out = {"n": M.n, "nnz": M.nnz, "n_traj": cnt, "log_permanent": lp}
+    for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
+        est.run(0, 64, seed, sch, want_logw=False, want_alive=False)
+        res, secs = timed_run(est, 0, cnt, seed, sch)
+        rec = summary(res["result"], secs)
+        le = rec["log_estimate"]
+        rec["log_error"] = le - lp
+        rec["rel_error"] = math.expm1(le - lp) if math.isfinite(le) else -1.0
+        out[name] = rec
+        print(f"[bench]   band n=1e5 {name}: rel error {rec['rel_error']:.3g}, {secs:.1f} s",
+              file=sys.stderr, flush=True)
+    est.close()
+    return out
 
 
 def main() -> int:
@@ -182,6 +268,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-compare", action="store_true", help="skip the plain run and the smaller-n ladder")
+    ap.add_argument("--ladder-seeds", type=int, default=5, help="run seeds replicated at n = 1e3 and 1e4")
+    ap.add_argument("--band-traj", type=int, default=10_000,
+                    help="trajectories per method on the n = 1e5 band matrix of known permanent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -205,7 +294,6 @@ def main() -> int:
               "(trajectories shard trivially by id, see the design notes)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2608_15390_amd as P
@@ -305,16 +393,22 @@ def main() -> int:
         est.run(0, 64, args.seed, other, want_logw=False, want_alive=False)
         res_o, secs = chunked_run(est, 0, n_traj, args.seed, other, max(1, n_traj // 4))
         mine = summary(r0, ms_per_step / 1e3)
+        mine["time_to_rse"] = time_to_rse(first_logw[0].cpu().numpy(),
+                                          first_logw[1].cpu().numpy().astype(bool), ms_per_step / 1e3)
         theirs = summary(res_o, secs)
+        theirs["time_to_rse"] = res_o["time_to_rse"]
         learned_s, plain_s = (mine, theirs) if args.method == "learned" else (theirs, mine)
         print("[bench] ladder n=1e3, 1e4", file=sys.stderr, flush=True)
-        lad = ladder(params, plain_sched, learned_sched, args.seed)
+        lad = ladder(params, plain_sched, learned_sched, [args.seed + i for i in range(args.ladder_seeds)])
+        print("[bench] band matrix n=1e5 (exact permanent known)", file=sys.stderr, flush=True)
+        band = band_study(params, plain_sched, learned_sched, args.seed, args.band_traj)
         line["compare"] = {
             "plain_schedule": args.plain_schedule,
             "learned": learned_s, "plain": plain_s,
             "ratio_learned_over_plain": learned_s["ess_per_s"] / plain_s["ess_per_s"],
             "degenerate": bool(learned_s["ess"] < 10 and plain_s["ess"] < 10),
             "ladder": lad,
+            "band": band,
         }
 
     if not args.no_cpu_baseline:
@@ -337,6 +431,17 @@ def main() -> int:
                 break
             count = min(n_traj, int(count * max(2.0, args.cpu_seconds / max(elapsed, 1e-3) / 2)))
         rate = count / elapsed
+        # single-thread rate on a few ids of the same sample
+        k1 = max(1, min(count, int(2 * count / (elapsed * threads) + 1)))
+        t = time.perf_counter()
+        O.run(A, osched, seed=args.seed, first=0, count=k1, nthreads=1, pre=pre)
+        rate1 = k1 / (time.perf_counter() - t)
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         lw, al = first_logw
         lw = lw[:count].cpu().numpy()
         al = al[:count].cpu().numpy()
@@ -350,6 +455,10 @@ def main() -> int:
             "sample": f"trajectory ids 0..{count - 1} of the timed batch ({count} of {n_traj}), "
                       f"{elapsed:.1f} s on {threads} threads; ESS/s = batch ESS x oracle traj/s / n_traj",
             "traj_per_s": rate,
+            "single_thread_traj_per_s": rate1,
+            "single_thread_ms_per_traj": 1e3 / rate1,
+            "cpu_model": cpu_model,
+            "host_cpus": os.cpu_count(),
             "matches_gpu": same,
         }
     print(json.dumps(line), flush=True)

@@ -25,6 +25,10 @@ Families (matrix order n, rows and columns both indexed 0..n-1):
   blocks of order 20 or 25 whose off-diagonal entries are deleted with
   probability p while the diagonal is kept (Sec. 4, "Matrices used"); the
   blocks are returned so a test can multiply exact block permanents.
+* ``banded``: entries within a band |i - j| <= w (diagonal always, the rest
+  kept with a given probability), rows and columns then randomly permuted;
+  the unpermuted band is returned so that a test or a stored reference can
+  compute the exact permanent by dynamic programming over the band, at any n.
 
 Everything is deterministic in the seed (numpy PCG64).
 """
@@ -39,8 +43,8 @@ __all__ = [
     "SparseMatrix", "from_coo", "from_dense", "to_dense",
     "identity", "permutation", "all_ones", "derangement", "upper_triangular",
     "grid", "planted_bernoulli", "planted_uniform", "power_law",
-    "hidden_block_diagonal", "uniform_nk", "bernoulli_nk", "with_weights",
-    "config_small", "config_batch", "config_large", "config_train",
+    "hidden_block_diagonal", "banded", "uniform_nk", "bernoulli_nk", "with_weights",
+    "config_small", "config_batch", "config_large", "config_train", "config_band",
     "config_stress",
 ]
 
@@ -303,6 +307,40 @@ def hidden_block_diagonal(n: int, p: float, seed: int, weighted: bool = False,
     M = from_coo(n, prow[rows], pcol[cols], vals if weighted else None,
                  meta={"family": "hidden_block_diagonal", "p": p, "orders": orders})
     return M, blocks
+
+
+def banded(n: int, half_width: int, keep: float, seed: int, weighted: bool = False):
+    """Band pattern |i - j| <= half_width with the diagonal always present and
+    every other band position kept with probability ``keep`` (values uniform
+    in [1, 1.5] as float32 when ``weighted``), then rows and columns permuted
+    uniformly at random.
+
+    Returns ``(matrix, band)``: ``band`` is the same matrix before the
+    permutation (row i holds only columns i - w .. i + w), and both have the
+    same permanent.  With half_width 4 and keep 7/8 the mean degree is 8.
+    """
+    g = _rng(seed, 12)
+    w = int(half_width)
+    off = np.arange(-w, w + 1, dtype=np.int64)
+    i = np.repeat(np.arange(n, dtype=np.int64), off.size)
+    j = i + np.tile(off, n)
+    draw = g.random(i.size)
+    vals = g.uniform(1.0, 1.5, size=i.size).astype(np.float32)
+    sel = (j >= 0) & (j < n) & ((j == i) | (draw < keep))
+    i, j, vals = i[sel], j[sel], vals[sel]
+    meta = {"family": "banded", "half_width": w, "keep": keep, "seed": seed}
+    band = from_coo(n, i, j, vals if weighted else None, meta=dict(meta, permuted=False))
+    prow = g.permutation(n)
+    pcol = g.permutation(n)
+    M = from_coo(n, prow[i], pcol[j], vals if weighted else None, meta=meta)
+    return M, band
+
+
+def config_band(seed: int = 1, n: int = 100_000):
+    """n = 1e5 band of half-width 4, off-diagonal band entries kept with
+    probability 7/8 (mean degree 8), randomly permuted: a large matrix of the
+    large workload's size and degree whose permanent is known exactly."""
+    return banded(n, 4, 0.875, seed)
 
 
 def with_weights(M: SparseMatrix, seed: int, lo: float = 1.0, hi: float = 1.5) -> SparseMatrix:

@@ -1,0 +1,53 @@
+"""Host-side statistics of the benchmark: the prefix RSE equals the oracle's
+RSE on the same trajectories, time-to-target follows the "first checkpoint
+after the last miss" rule, and the bootstrap interval brackets the mean."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import bench
+from oracle import oracle as O
+
+
+def _sample(M, seed):
+    g = np.random.default_rng(seed)
+    lw = g.normal(3.0, 1.5, size=M)
+    al = g.random(M) < 0.7
+    lw[~al] = -np.inf
+    return lw, al
+
+
+def test_prefix_rse_matches_oracle_statistics():
+    lw, al = _sample(5000, 1)
+    for m in (2, 17, 1024, 5000):
+        st = O.stats(lw[:m], al[:m].astype(np.uint8))
+        assert bench.prefix_rse(lw, al, m) == pytest.approx(st["rse"], rel=1e-10)
+    assert bench.prefix_rse(lw, np.zeros(5000, dtype=bool), 100) == math.inf
+
+
+def test_time_to_rse_rule():
+    lw, al = _sample(1 << 14, 2)
+    out = bench.time_to_rse(lw, al, 8.0, eps_list=(1.0, 1e-2, 1e-9))
+    assert out["1e-09"] is None
+    M = lw.size
+    cps = [1 << k for k in range(1, 14)] + [M]
+    for key, eps in (("1", 1.0), ("0.01", 1e-2)):
+        rses = [bench.prefix_rse(lw, al, c) for c in cps]
+        last_bad = max([i for i, r in enumerate(rses) if r > eps], default=-1)
+        if last_bad == len(cps) - 1:
+            assert out[key] is None
+        else:
+            c = cps[last_bad + 1]
+            assert out[key]["trajectories"] == c
+            assert out[key]["seconds"] == pytest.approx(8.0 * c / M)
+
+
+def test_bootstrap_interval_brackets_the_mean():
+    v = [0.9, 1.1, 1.0, 0.95, 1.05]
+    lo, hi = bench.bootstrap_ci(v)
+    assert lo <= np.mean(v) <= hi
+    assert min(v) <= lo and hi <= max(v)
+    assert bench.bootstrap_ci([2.0] * 5) == [2.0, 2.0]

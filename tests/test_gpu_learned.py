@@ -128,6 +128,8 @@ def _learned_mats():
     mats = G.config_batch(4, count=6, nmin=30, nmax=120)
     # one matrix with vertex lists longer than a wave (the multi-chunk path)
     mats.append(G.planted_bernoulli(90, 0.85, 17, planted="random"))
+    # a permuted band matrix (regular local structure, many equal degrees)
+    mats.append(G.banded(150, 4, 0.875, 18)[0])
     return mats
 
 
@@ -193,13 +195,18 @@ def test_learned_needs_a_model_and_rejects_bad_ones():
 
 def test_learned_estimates_are_unbiased():
     import paper_2608_15390_amd as P
+    from oracle import band as B
     mats = [G.config_small(s) for s in range(1, 7)]
-    pers = [O.ryser(G.to_dense(M)) for M in mats]
+    lpers = [math.log(O.ryser(G.to_dense(M))) for M in mats]
+    # and a band matrix beyond Ryser's reach (n = 60), exact by the band recursion
+    Mb, band = G.banded(60, 3, 0.8, 8)
+    mats.append(Mb)
+    lpers.append(B.band_log_permanent(band, 3))
     bt = P.PermEstBatch(mats)
     bt.set_model(_dev(R.quantize(R.init(13)), torch.float32))
     out = bt.run(50000, 9, P.preset("learned"), want_logw=False, want_alive=False)
-    for r, per in zip(out["results"], pers):
-        assert abs(math.exp(r["log_estimate"]) / per - 1) <= 4.5 * r["rse"]
+    for r, lp in zip(out["results"], lpers):
+        assert abs(math.exp(r["log_estimate"] - lp) - 1) <= 4.5 * r["rse"], (r, lp)
     bt.close()
 
 

@@ -69,7 +69,8 @@ def _compare(M, gsched, osched, seed, first, count, force_hbm=False, path=True):
 
 SMALL = [("small1", lambda: G.config_small(1)), ("small2", lambda: G.config_small(2)),
          ("weighted", lambda: G.with_weights(G.planted_bernoulli(40, 0.12, 5, planted="random"), 1)),
-         ("grid6x6", lambda: G.grid(6, 6))]
+         ("grid6x6", lambda: G.grid(6, 6)),
+         ("band", lambda: G.banded(50, 3, 0.8, 4)[0])]
 
 
 def test_small_workload_plain_bit_exact():
@@ -124,6 +125,30 @@ def test_full_size_large_workload_sampled_ids():
     g, o = _both("local_nodm")
     for first in (0, 65535, 99998):
         _compare(M, g, o, seed=1, first=first, count=2, path=True)
+
+
+def test_full_size_band_workload_sampled_ids():
+    """n = 1e5 band matrix of mean degree 8 (the exactly known workload):
+    sampled trajectory ids against the oracle, plain and local repair."""
+    M, _ = G.config_band(1)
+    for name in ("plain", "local_nodm"):
+        g, o = _both(name)
+        for first in (0, 77777):
+            _compare(M, g, o, seed=1, first=first, count=2, path=True)
+
+
+@pytest.mark.parametrize("name,n", [("plain", 100), ("local_nodm", 200), ("local_threshold", 200)])
+def test_gpu_mean_within_ci_of_band_permanent(name, n):
+    """E[X] = per(A) (Sec. 2) at n = 100 and 200, beyond Ryser's reach: the
+    exact value comes from the dynamic program over the band."""
+    import paper_2608_15390_amd as P
+    from oracle import band as B
+    M, band = G.banded(n, 3, 0.8, 7)
+    lp = B.band_log_permanent(band, 3)
+    est = P.PermEst(M)
+    r = est.run(0, 200000, 31, P.preset(name), want_logw=False, want_alive=False)["result"]
+    est.close()
+    assert abs(math.exp(r["log_estimate"] - lp) - 1) <= 4.5 * r["rse"], (name, r, lp)
 
 
 @pytest.mark.parametrize("name", ["plain", "local_nodm", "adaptive_nodm"])
@@ -185,7 +210,8 @@ def test_gpu_mean_within_ci_of_ryser(gseed):
 PAPER_PRESETS = ["fixed_all", "adaptive_threshold", "local_threshold", "adaptive_tracked", "local_tracked"]
 DM_MATS = [("small1", lambda: G.config_small(1)), ("small3", lambda: G.config_small(3)),
            ("weighted", lambda: G.with_weights(G.planted_bernoulli(40, 0.12, 5, planted="random"), 1)),
-           ("batch60", lambda: G.planted_bernoulli(60, 5.0 / 59, 21, planted="random"))]
+           ("batch60", lambda: G.planted_bernoulli(60, 5.0 / 59, 21, planted="random")),
+           ("band", lambda: G.banded(50, 3, 0.8, 4)[0])]
 
 
 @pytest.mark.parametrize("name", PAPER_PRESETS)

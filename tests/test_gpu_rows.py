@@ -25,6 +25,7 @@ CASES = [
     ("weighted", lambda: G.with_weights(G.planted_bernoulli(260, 5.0 / 260, 32, planted="random"), 4)),
     ("long_lists", lambda: G.planted_bernoulli(90, 0.5, 33, planted="random")),
     ("power_law", lambda: G.power_law(3000, 34)),
+    ("band", lambda: G.banded(400, 4, 0.875, 35)[0]),
     ("no_matching", lambda: G.from_coo(40, np.r_[np.arange(39), 0], np.r_[np.arange(39), 1])),
 ]
 

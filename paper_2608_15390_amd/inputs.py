@@ -26,7 +26,8 @@ Families (matrix order n, rows and columns both indexed 0..n-1):
   probability p while the diagonal is kept (Sec. 4, "Matrices used"); the
   blocks are returned so a test can multiply exact block permanents.
 * ``banded``: entries within a band |i - j| <= w (diagonal always, the rest
-  kept with a given probability), rows and columns then randomly permuted;
+  -- or only the outermost diagonals -- kept with a given probability), rows
+  and columns then randomly permuted;
   the unpermuted band is returned so that a test or a stored reference can
   compute the exact permanent by dynamic programming over the band, at any n.
 
@@ -309,15 +310,17 @@ def hidden_block_diagonal(n: int, p: float, seed: int, weighted: bool = False,
     return M, blocks
 
 
-def banded(n: int, half_width: int, keep: float, seed: int, weighted: bool = False):
+def banded(n: int, half_width: int, keep: float, seed: int, weighted: bool = False,
+           outer_only: bool = False):
     """Band pattern |i - j| <= half_width with the diagonal always present and
-    every other band position kept with probability ``keep`` (values uniform
-    in [1, 1.5] as float32 when ``weighted``), then rows and columns permuted
-    uniformly at random.
+    band positions kept with probability ``keep`` (every off-diagonal band
+    position, or with ``outer_only`` only those with |i - j| = half_width,
+    the rest of the band being full), values uniform in [1, 1.5] as float32
+    when ``weighted``; then rows and columns permuted uniformly at random.
 
     Returns ``(matrix, band)``: ``band`` is the same matrix before the
     permutation (row i holds only columns i - w .. i + w), and both have the
-    same permanent.  With half_width 4 and keep 7/8 the mean degree is 8.
+    same permanent.
     """
     g = _rng(seed, 12)
     w = int(half_width)
@@ -326,9 +329,10 @@ def banded(n: int, half_width: int, keep: float, seed: int, weighted: bool = Fal
     j = i + np.tile(off, n)
     draw = g.random(i.size)
     vals = g.uniform(1.0, 1.5, size=i.size).astype(np.float32)
-    sel = (j >= 0) & (j < n) & ((j == i) | (draw < keep))
+    full = np.abs(j - i) < w if outer_only else j == i
+    sel = (j >= 0) & (j < n) & (full | (draw < keep))
     i, j, vals = i[sel], j[sel], vals[sel]
-    meta = {"family": "banded", "half_width": w, "keep": keep, "seed": seed}
+    meta = {"family": "banded", "half_width": w, "keep": keep, "outer_only": outer_only, "seed": seed}
     band = from_coo(n, i, j, vals if weighted else None, meta=dict(meta, permuted=False))
     prow = g.permutation(n)
     pcol = g.permutation(n)
@@ -337,10 +341,13 @@ def banded(n: int, half_width: int, keep: float, seed: int, weighted: bool = Fal
 
 
 def config_band(seed: int = 1, n: int = 100_000):
-    """n = 1e5 band of half-width 4, off-diagonal band entries kept with
-    probability 7/8 (mean degree 8), randomly permuted: a large matrix of the
-    large workload's size and degree whose permanent is known exactly."""
-    return banded(n, 4, 0.875, seed)
+    """n = 1e5 band of half-width 4 whose inner band (|i - j| <= 3) is full
+    and whose outermost diagonals keep each entry with probability 1/2 (mean
+    degree 8), randomly permuted: a matrix of the large workload's size and
+    degree whose permanent is known exactly.  (Thinning the whole band
+    instead leaves vertices that lose all their neighbours, and at this n
+    every trajectory dies.)"""
+    return banded(n, 4, 0.5, seed, outer_only=True)
 
 
 def with_weights(M: SparseMatrix, seed: int, lo: float = 1.0, hi: float = 1.5) -> SparseMatrix:

@@ -1,6 +1,6 @@
 """Writes band_n1e5_hw4.json: the exact ln per(A) of the n = 1e5 band matrix
-of mean degree 8 (half-width 4, off-diagonal band entries kept with
-probability 7/8, rows and columns permuted; generator seed 1), computed by
+of mean degree 8 (half-width 4, inner band full, outermost diagonals kept
+with probability 1/2, rows and columns permuted; generator seed 1), computed by
 the oracle's dynamic program over the band.  The index arrays' digest is
 stored with it so that a reader can tell that the generator still builds the
 same matrix.
@@ -31,7 +31,7 @@ def digest(M) -> str:
 def main() -> None:
     M, band = G.config_band(1)
     out = {
-        "matrix": "inputs.config_band(seed=1): n = 1e5, band half-width 4, keep 7/8, permuted",
+        "matrix": "inputs.config_band(seed=1): n = 1e5, band half-width 4, outer diagonals kept with probability 1/2, permuted",
         "n": M.n,
         "nnz": M.nnz,
         "index_sha256": digest(M),

@@ -50,6 +50,9 @@ def test_band_dp_matches_ryser(w, keep):
         assert B.band_permanent_exact(band) == per
         lp = B.band_log_permanent(band)
         assert lp == (pytest.approx(math.log(per), rel=1e-13) if per else -math.inf)
+        Mo, bo = G.banded(18, w, keep, 30 + seed, outer_only=True)
+        per = O.ryser(G.to_dense(bo))
+        assert O.ryser(G.to_dense(Mo)) == per and B.band_permanent_exact(bo) == per
         Mw, bw = G.banded(16, w, keep, 20 + seed, weighted=True)
         pw = O.ryser_f64(G.to_dense(bw))
         assert B.band_log_permanent(bw) == pytest.approx(math.log(pw), rel=1e-12)

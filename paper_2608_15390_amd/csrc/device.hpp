@@ -12,6 +12,36 @@ constexpr double kLn2 = 0.69314718055994530941723212145818;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// ------------------------------------------------------------ address spaces
+// A pointer the compiler cannot trace to its allocation (one loaded from an
+// argument block) is generic, and its accesses become flat instructions.
+// Those count against the LDS wait counter as well as the vector-memory one,
+// so every LDS access or cross-lane exchange that waits for its result would
+// also wait for all outstanding HBM loads and stores. Device code therefore
+// re-types such pointers as global (address space 1) or LDS (3) ones.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PE_G __attribute__((address_space(1)))
+#define PE_L __attribute__((address_space(3)))
+#else
+#define PE_G
+#define PE_L
+#endif
+constexpr int kAsGlobal = 1, kAsLds = 3;
+template <int AS, class T> struct AsPtr { using type = PE_G T *; };
+template <class T> struct AsPtr<kAsLds, T> { using type = PE_L T *; };
+template <int AS, class T> using as_ptr = typename AsPtr<AS, T>::type;
+template <int AS, class T>
+__device__ __forceinline__ as_ptr<AS, T> to_as(T *p) { return (as_ptr<AS, T>)p; }
+template <class T>
+__device__ __forceinline__ PE_G T *gptr(T *p) { return (PE_G T *)p; }
+// the same address space with another element type
+template <class U, class T>
+__device__ __forceinline__ PE_G U *recast(PE_G T *p) { return (PE_G U *)p; }
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class U, class T>
+__device__ __forceinline__ PE_L U *recast(PE_L T *p) { return (PE_L U *)p; }
+#endif
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Order this wave's earlier LDS / global accesses before its later ones

@@ -102,25 +102,26 @@ __device__ __forceinline__ int row_owner(int32_t f, int32_t off) {
 
 // One row's trajectory state and views (all values uniform within the row).
 struct RowTraj {
-    const TrajArgs &a;
-    uint16_t *deg;
-    int32_t *lst_a, *lst_b;
+    const PE_G TrajArgs &a;
+    GMat M;
+    PE_G uint16_t *deg;
+    PE_G int32_t *lst_a, *lst_b;
     uint32_t *tree;
     int32_t n;
 
     __device__ uint32_t *level(int k) const { return tree + a.tree.off[k]; }
     __device__ void list(int32_t x, int32_t &b, int32_t &e) const {
-        if (x < n) { b = a.A.row_ptr[x]; e = a.A.row_ptr[x + 1]; }
-        else { b = a.A.col_ptr[x - n]; e = a.A.col_ptr[x - n + 1]; }
+        if (x < n) { b = M.row_ptr[x]; e = M.row_ptr[x + 1]; }
+        else { b = M.col_ptr[x - n]; e = M.col_ptr[x - n + 1]; }
     }
     template <bool WT>
     __device__ void entry(bool row, int32_t p, int32_t &y, float &bv) const {
-        if (row) { y = n + a.A.col_idx[p]; bv = WT ? a.A.val[p] : 1.0f; }
-        else { y = a.A.row_idx[p]; bv = WT ? a.A.val_csc[p] : 1.0f; }
+        if (row) { y = n + M.col_idx[p]; bv = WT ? M.val[p] : 1.0f; }
+        else { y = M.row_idx[p]; bv = WT ? M.val_csc[p] : 1.0f; }
     }
     __device__ float scale0(int32_t y) const {
-        if (y < n) return a.r0 ? a.r0[y] : 1.0f;
-        return a.c0 ? a.c0[y - n] : 1.0f;
+        if (y < n) return a.r0 ? gptr(a.r0)[y] : 1.0f;
+        return a.c0 ? gptr(a.c0)[y - n] : 1.0f;
     }
     __device__ void tree_lower(int32_t x, uint32_t d) const {
         atomicMin(level(0) + (x >> 8), d);
@@ -147,7 +148,7 @@ struct RowTraj {
     }
     // this lane's 16 leaves of group g (vertices 256 g + 16 rl .. + 15)
     __device__ void load_leaves(int32_t g, uint4 &q0, uint4 &q1) const {
-        const uint4 *p = reinterpret_cast<const uint4 *>(deg + 256 * g + 16 * row_lane());
+        const auto p = recast<const uint4>(deg + 256 * g + 16 * row_lane());
         q0 = p[0];
         q1 = p[1];
     }
@@ -213,17 +214,17 @@ __device__ __forceinline__ uint64_t scaled_weight(float s, float smax, bool unif
 template <bool WT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 traj_rows_kernel(const BatchArgs *__restrict__ bp) {
-    const BatchArgs &B = *bp;
-    const TrajArgs &a = B.mats[0];
+    const PE_G BatchArgs &B = *gptr(bp);
+    const PE_G TrajArgs &a = gptr(B.mats)[0];
     extern __shared__ __align__(16) char smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int r = row_id(), rl = row_lane();
     const int32_t n = a.A.n;
     char *mine = smem + (size_t)wave * 4 * (size_t)B.lds_tree_bytes;
-    char *state = B.hbm_state + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
-    const StateLayout &L = a.st;
-    const RowTraj T{a, reinterpret_cast<uint16_t *>(state + L.deg), reinterpret_cast<int32_t *>(state + L.lst_a),
-                    reinterpret_cast<int32_t *>(state + L.lst_b),
+    PE_G char *state = gptr(B.hbm_state) + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
+    const auto &L = a.st;
+    const RowTraj T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
+                    recast<int32_t>(state + L.lst_b),
                     reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes), n};
     Work work;
     // per-row trajectory registers (uniform within the row)
@@ -240,7 +241,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
         // ---- claim and initialise (rows that finished their trajectory)
         if (phase == 0) {
             uint32_t qq = 0;
-            if (rl == 0) qq = atomicAdd(B.work_next, 1u);
+            if (rl == 0) qq = atomicAdd(gptr(B.work_next), 1u);
             qq = row_bcast<0>(qq);
             if ((int64_t)qq >= B.total) {
                 phase = 2;
@@ -254,10 +255,10 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 ex = 0;
                 h = 0;
                 alive = a.ok0 != 0;
-                const uint4 *src = reinterpret_cast<const uint4 *>(a.deg0);
-                uint4 *dst = reinterpret_cast<uint4 *>(T.deg);
+                const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
+                const auto dst = recast<uint4>(T.deg);
                 for (int32_t i = rl; i < a.n_leaf / 8; i += kRowLanes) dst[i] = src[i];
-                for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = a.tree0[i];
+                for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = gptr(a.tree0)[i];
                 wave_fence();
             }
         }

@@ -36,6 +36,15 @@ struct DevMat {
     const float *val_csc;     // CSC order, nullptr = 0/1
 };
 
+// the matrix arrays as global-memory pointers (device code)
+struct GMat {
+    const PE_G int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *csc2csr, *edge_row;
+    const PE_G float *val, *val_csc;
+    __device__ explicit GMat(const PE_G DevMat &A)
+        : row_ptr(gptr(A.row_ptr)), col_idx(gptr(A.col_idx)), col_ptr(gptr(A.col_ptr)), row_idx(gptr(A.row_idx)),
+          csc2csr(gptr(A.csc2csr)), edge_row(gptr(A.edge_row)), val(gptr(A.val)), val_csc(gptr(A.val_csc)) {}
+};
+
 struct TreeLayout {
     int32_t levels;   // internal levels, 1..3
     int32_t size[3];  // nodes per level (level 1 first)
@@ -98,32 +107,37 @@ struct TrajArgs {
 };
 
 // ------------------------------------------------------------------ views
-template <bool OWN, bool DM, bool WT>
+// AS: address space of the trajectory's state (kAsLds: the wave's LDS
+// slot, kAsGlobal: its HBM slot)
+template <bool OWN, bool DM, bool WT, int AS>
 struct Traj {
-    const TrajArgs &a;
-    uint16_t *deg;
+    const PE_G TrajArgs &a;
+    GMat M;
+    const PE_G float *r0, *c0;  // shared outer scaling, nullptr = all ones
+    as_ptr<AS, uint16_t> deg;
     uint32_t *tree;
-    Rec *rec;
-    int32_t *lst_a, *lst_b, *loc_r, *loc_c;
-    float *new_v;
-    uint32_t *rem;
-    int32_t *mate_r, *mate_c, *ws;
+    as_ptr<AS, Rec> rec;
+    as_ptr<AS, int32_t> lst_a, lst_b, loc_r, loc_c;
+    as_ptr<AS, float> new_v;
+    as_ptr<AS, uint32_t> rem;
+    as_ptr<AS, int32_t> mate_r, mate_c, ws;
     int32_t n;
 
-    __device__ Traj(const TrajArgs &args, char *state, uint32_t *tree_lds)
-        : a(args), tree(tree_lds), n(args.A.n) {
-        const StateLayout &s = args.st;
-        deg = reinterpret_cast<uint16_t *>(state + s.deg);
-        rec = OWN ? reinterpret_cast<Rec *>(state + s.rec) : nullptr;
-        lst_a = reinterpret_cast<int32_t *>(state + s.lst_a);
-        lst_b = reinterpret_cast<int32_t *>(state + s.lst_b);
-        loc_r = reinterpret_cast<int32_t *>(state + s.loc_r);
-        loc_c = reinterpret_cast<int32_t *>(state + s.loc_c);
-        new_v = reinterpret_cast<float *>(state + s.new_v);
-        rem = DM ? reinterpret_cast<uint32_t *>(state + s.rem) : nullptr;
-        mate_r = reinterpret_cast<int32_t *>(state + s.mate_r);
-        mate_c = reinterpret_cast<int32_t *>(state + s.mate_c);
-        ws = reinterpret_cast<int32_t *>(state + s.ws);
+    __device__ Traj(const PE_G TrajArgs &args, char *state_any, uint32_t *tree_lds)
+        : a(args), M(args.A), r0(gptr(args.r0)), c0(gptr(args.c0)), tree(tree_lds), n(args.A.n) {
+        const auto &s = args.st;
+        const auto state = to_as<AS>(state_any);
+        deg = recast<uint16_t>(state + s.deg);
+        rec = OWN ? recast<Rec>(state + s.rec) : nullptr;
+        lst_a = recast<int32_t>(state + s.lst_a);
+        lst_b = recast<int32_t>(state + s.lst_b);
+        loc_r = recast<int32_t>(state + s.loc_r);
+        loc_c = recast<int32_t>(state + s.loc_c);
+        new_v = recast<float>(state + s.new_v);
+        rem = DM ? recast<uint32_t>(state + s.rem) : nullptr;
+        mate_r = recast<int32_t>(state + s.mate_r);
+        mate_c = recast<int32_t>(state + s.mate_c);
+        ws = recast<int32_t>(state + s.ws);
     }
 
     __device__ __forceinline__ bool active(int32_t x) const { return deg[x] != kRetired; }
@@ -134,23 +148,23 @@ struct Traj {
     // scaling value of vertex y (r_y for a row, c_{y-n} for a column)
     __device__ __forceinline__ float scale(int32_t y) const {
         if (OWN) return rec[y].s;
-        if (y < n) return a.r0 ? a.r0[y] : 1.0f;
-        return a.c0 ? a.c0[y - n] : 1.0f;
+        if (y < n) return r0 ? r0[y] : 1.0f;
+        return c0 ? c0[y - n] : 1.0f;
     }
     __device__ __forceinline__ void list(int32_t x, int32_t &beg, int32_t &end) const {
-        if (x < n) { beg = a.A.row_ptr[x]; end = a.A.row_ptr[x + 1]; }
-        else { beg = a.A.col_ptr[x - n]; end = a.A.col_ptr[x - n + 1]; }
+        if (x < n) { beg = M.row_ptr[x]; end = M.row_ptr[x + 1]; }
+        else { beg = M.col_ptr[x - n]; end = M.col_ptr[x - n + 1]; }
     }
     // entry p of a list: neighbour vertex id, CSR edge id, value
     __device__ __forceinline__ void entry(bool row, int32_t p, int32_t &y, int32_t &e, float &bv) const {
         if (row) {
-            y = n + a.A.col_idx[p];
+            y = n + M.col_idx[p];
             e = p;
-            bv = WT ? a.A.val[p] : 1.0f;
+            bv = WT ? M.val[p] : 1.0f;
         } else {
-            y = a.A.row_idx[p];
-            e = DM ? a.A.csc2csr[p] : 0;
-            bv = WT ? a.A.val_csc[p] : 1.0f;
+            y = M.row_idx[p];
+            e = DM ? M.csc2csr[p] : 0;
+            bv = WT ? M.val_csc[p] : 1.0f;
         }
     }
 
@@ -165,7 +179,7 @@ struct Traj {
 
     __device__ __forceinline__ uint32_t leaf_group_min(int32_t g) const {
         const int l = lane_id();
-        const uint2 q = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
+        const uint2 q = recast<const uint2>(deg + 256 * g)[l];
         uint32_t m = min(min(q.x & 0xFFFFu, q.x >> 16), min(q.y & 0xFFFFu, q.y >> 16));
         return wave_min_u32(m);
     }
@@ -237,15 +251,15 @@ struct Traj {
             g = 64 * g + __ffsll((unsigned long long)hit) - 1;
         }
         if (!hit) return false;
-        leaves = reinterpret_cast<const uint2 *>(deg + 256 * g)[l];
+        leaves = recast<const uint2>(deg + 256 * g)[l];
         int32_t lb[4], le[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int32_t x = 256 * g + 4 * l + i;
             lb[i] = 0;
             le[i] = 0;
-            if (x < n) { lb[i] = a.A.row_ptr[x]; le[i] = a.A.row_ptr[x + 1]; }
-            else if (x < 2 * n) { lb[i] = a.A.col_ptr[x - n]; le[i] = a.A.col_ptr[x - n + 1]; }
+            if (x < n) { lb[i] = M.row_ptr[x]; le[i] = M.row_ptr[x + 1]; }
+            else if (x < 2 * n) { lb[i] = M.col_ptr[x - n]; le[i] = M.col_ptr[x - n + 1]; }
         }
         const uint32_t d0 = leaves.x & 0xFFFFu, d1 = leaves.x >> 16, d2 = leaves.y & 0xFFFFu,
                        d3 = leaves.y >> 16;
@@ -271,11 +285,11 @@ struct Traj {
         for (int32_t j = l; j < n; j += kWave) {
             if (!active(n + j)) continue;
             float acc = 0.0f;
-            for (int32_t p = a.A.col_ptr[j]; p < a.A.col_ptr[j + 1]; ++p) {
-                const int32_t i = a.A.row_idx[p];
+            for (int32_t p = M.col_ptr[j]; p < M.col_ptr[j + 1]; ++p) {
+                const int32_t i = M.row_idx[p];
                 if (!active(i)) continue;
-                if (DM && removed(a.A.csc2csr[p])) continue;
-                const float bv = WT ? a.A.val_csc[p] : 1.0f;
+                if (DM && removed(M.csc2csr[p])) continue;
+                const float bv = WT ? M.val_csc[p] : 1.0f;
                 const float prod = bv * rec[i].s;
                 acc = acc + prod;
             }
@@ -285,10 +299,10 @@ struct Traj {
         for (int32_t i = l; i < n; i += kWave) {
             if (!active(i)) continue;
             float acc = 0.0f;
-            for (int32_t e = a.A.row_ptr[i]; e < a.A.row_ptr[i + 1]; ++e) {
-                const int32_t j = a.A.col_idx[e];
+            for (int32_t e = M.row_ptr[i]; e < M.row_ptr[i + 1]; ++e) {
+                const int32_t j = M.col_idx[e];
                 if (!active(n + j) || removed(e)) continue;
-                const float bv = WT ? a.A.val[e] : 1.0f;
+                const float bv = WT ? M.val[e] : 1.0f;
                 const float prod = bv * rec[n + j].s;
                 acc = acc + prod;
             }
@@ -309,7 +323,7 @@ struct Traj {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int32_t p = p0 + i < end ? p0 + i : end - 1;
-                y[i] = row ? n + a.A.col_idx[p] : a.A.row_idx[p];
+                y[i] = row ? n + M.col_idx[p] : M.row_idx[p];
             }
             float sv[8];
 #pragma unroll
@@ -319,10 +333,10 @@ struct Traj {
                 const int32_t p = p0 + i;
                 if (p < end && sv[i] >= 0.0f) {
                     if (DM) {
-                        const int32_t e = row ? p : a.A.csc2csr[p];
+                        const int32_t e = row ? p : M.csc2csr[p];
                         if (removed(e)) continue;
                     }
-                    const float bv = WT ? (row ? a.A.val[p] : a.A.val_csc[p]) : 1.0f;
+                    const float bv = WT ? (row ? M.val[p] : M.val_csc[p]) : 1.0f;
                     const float prod = bv * sv[i];
                     acc = acc + prod;
                 }
@@ -340,14 +354,15 @@ struct Traj {
     // off the matching whose endpoints lie in different components.
     // Sequential parts run on lane 0; returns false if the child has no
     // perfect matching.
-    __device__ bool augment_from(int32_t s, int32_t *queue, int32_t *parent, int32_t *vis,
+    __device__ bool augment_from(int32_t s, as_ptr<AS, int32_t> queue, as_ptr<AS, int32_t> parent,
+                                 as_ptr<AS, int32_t> vis,
                                  int32_t stamp) const {
         int32_t head = 0, tail = 0, found = -1;
         queue[tail++] = s;
         while (head < tail && found < 0) {
             const int32_t i = queue[head++];
-            for (int32_t e = a.A.row_ptr[i]; e < a.A.row_ptr[i + 1]; ++e) {
-                const int32_t j = a.A.col_idx[e];
+            for (int32_t e = M.row_ptr[i]; e < M.row_ptr[i + 1]; ++e) {
+                const int32_t j = M.col_idx[e];
                 if (!active(n + j) || removed(e) || vis[j] == stamp) continue;
                 vis[j] = stamp;
                 parent[j] = i;
@@ -369,7 +384,7 @@ struct Traj {
     }
 
     __device__ bool dm_sequential() const {
-        int32_t *queue = ws, *parent = ws + n, *vis = ws + 2 * n;
+        const auto queue = ws, parent = ws + n, vis = ws + 2 * n;
         for (int32_t j = 0; j < n; ++j) {
             vis[j] = 0;
             if (active(n + j) && mate_c[j] >= 0 && !active(mate_c[j])) mate_c[j] = -1;
@@ -383,30 +398,30 @@ struct Traj {
             if (!augment_from(i, queue, parent, vis, ++stamp)) return false;
         }
         // Tarjan over active rows; comp[x] = id of x's component
-        int32_t *idx = ws, *low = ws + n, *comp = ws + 2 * n, *stk = ws + 3 * n, *fnode = ws + 4 * n,
-                *fpos = ws + 5 * n;
+        const auto idx = ws, low = ws + n, comp = ws + 2 * n, stk = ws + 3 * n, fnode = ws + 4 * n,
+                fpos = ws + 5 * n;
         for (int32_t i = 0; i < n; ++i) { idx[i] = -1; comp[i] = -1; }
         int32_t counter = 0, sp = 0;
         for (int32_t root = 0; root < n; ++root) {
             if (!active(root) || idx[root] >= 0) continue;
             int32_t top = 0;
             fnode[0] = root;
-            fpos[0] = a.A.col_ptr[mate_r[root]];
+            fpos[0] = M.col_ptr[mate_r[root]];
             idx[root] = low[root] = counter++;
             stk[sp++] = root;
             while (top >= 0) {
                 const int32_t x = fnode[top];
                 const int32_t jm = mate_r[x];
-                const int32_t end = a.A.col_ptr[jm + 1];
+                const int32_t end = M.col_ptr[jm + 1];
                 bool descended = false;
                 while (fpos[top] < end) {
                     const int32_t p = fpos[top]++;
-                    const int32_t y = a.A.row_idx[p];
-                    if (y == x || !active(y) || removed(a.A.csc2csr[p])) continue;
+                    const int32_t y = M.row_idx[p];
+                    if (y == x || !active(y) || removed(M.csc2csr[p])) continue;
                     if (idx[y] < 0) {
                         ++top;
                         fnode[top] = y;
-                        fpos[top] = a.A.col_ptr[mate_r[y]];
+                        fpos[top] = M.col_ptr[mate_r[y]];
                         idx[y] = low[y] = counter++;
                         stk[sp++] = y;
                         descended = true;
@@ -430,15 +445,15 @@ struct Traj {
     // components (bitmap words in parallel), recount degrees, rebuild tree
     __device__ void dm_apply() const {
         const int l = lane_id();
-        const int32_t *comp = ws + 2 * n;
+        const auto comp = ws + 2 * n;
         const int32_t words = (a.A.m + 31) / 32;
         for (int32_t w = l; w < words; w += kWave) {
             uint32_t bits = rem[w];
             for (int32_t b = 0; b < 32; ++b) {
                 const int32_t e = 32 * w + b;
                 if (e >= a.A.m || ((bits >> b) & 1u)) continue;
-                const int32_t i = a.A.edge_row[e];
-                const int32_t j = a.A.col_idx[e];
+                const int32_t i = M.edge_row[e];
+                const int32_t j = M.col_idx[e];
                 if (!active(i) || !active(n + j) || mate_r[i] == j) continue;
                 if (comp[i] != comp[mate_c[j]]) bits |= 1u << b;
             }
@@ -510,7 +525,7 @@ __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total)
 template <class TT>
 __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
                                                    Work &work) {
-    const TrajArgs &a = T.a;
+    const auto &a = T.a;
     const int l = lane_id();
     const int32_t n = T.n;
     const int32_t mark = t + 1;
@@ -525,8 +540,8 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
         nr = __popcll(mr);
     }
     int32_t gb = 0, gl = 0, rb = 0, rl = 0;
-    if (gam_y >= 0) { gb = a.A.row_ptr[gam_y]; gl = a.A.row_ptr[gam_y + 1] - gb; }
-    if (rho_y >= 0) { rb = a.A.col_ptr[rho_y - n]; rl = a.A.col_ptr[rho_y - n + 1] - rb; }
+    if (gam_y >= 0) { gb = T.M.row_ptr[gam_y]; gl = T.M.row_ptr[gam_y + 1] - gb; }
+    if (rho_y >= 0) { rb = T.M.col_ptr[rho_y - n]; rl = T.M.col_ptr[rho_y - n + 1] - rb; }
     int32_t TG, TR;
     const int32_t og = wave_excl_scan_i32(gl, TG);
     const int32_t orr = wave_excl_scan_i32(rl, TR);
@@ -545,12 +560,12 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
         int32_t tgt = -1, e = 0;
         if (in_g) {
             const int32_t p = gb_o + (fg - og_v);
-            tgt = n + a.A.col_idx[p];
+            tgt = n + T.M.col_idx[p];
             e = p;
         } else if (in_r) {
             const int32_t p = rb_o + (fr - or_v);
-            tgt = a.A.row_idx[p];
-            e = T.rem ? a.A.csc2csr[p] : 0;
+            tgt = T.M.row_idx[p];
+            e = T.rem ? T.M.csc2csr[p] : 0;
         }
         bool cand = false;
         if (tgt >= 0) {
@@ -607,9 +622,9 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
 
 // Eq. (local) with lists kept in memory (either list longer than a wave):
 // the same sets and values, built one list at a time.
-template <class TT>
-__device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t k_rho, int32_t skip_rho,
-                                   const int32_t *gam_list, int32_t k_gam, int32_t skip_gam, int32_t t,
+template <class TT, class LP>
+__device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int32_t skip_rho,
+                                   LP gam_list, int32_t k_gam, int32_t skip_gam, int32_t t,
                                    Work &work) {
     const int l = lane_id();
     const int32_t n = T.n;
@@ -634,7 +649,7 @@ __device__ void local_repair_lists(const TT &T, const int32_t *rho_list, int32_t
     }
     wave_fence();
     // child neighbours, one source vertex at a time (its entries are distinct)
-    auto gather = [&](int32_t x, int32_t *out, int32_t &cnt, bool to_col) {
+    auto gather = [&](int32_t x, auto out, int32_t &cnt, bool to_col) {
         int32_t beg, end;
         T.list(x, beg, end);
         const bool row = x < n;
@@ -842,8 +857,8 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
     return cand ? mine : 0;
 }
 
-template <int SK, bool DM, bool WT>
-__device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT> &T,
+template <int SK, bool DM, bool WT, int AS>
+__device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT, AS> &T,
                                                int64_t q, Work &work, const LearnedLds *lrn, TileLds *mlps) {
     const MlpLds *mlpw = &lrn->net;
     const uint32_t *etab = lrn->etab;
@@ -851,27 +866,27 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
     const int l = lane_id();
     const int32_t n = a.A.n;
     const uint32_t k = (uint32_t)(a.first + q);
-    int32_t *path = a.path ? a.path + (size_t)q * 2 * n : nullptr;
+    PE_G int32_t *path = a.path ? gptr(a.path) + (size_t)q * 2 * n : nullptr;
 
     // ---- initial state: template degrees, tree, scaling values, matching
     {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.deg0);
-        uint4 *dst = reinterpret_cast<uint4 *>(T.deg);
+        const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
+        const auto dst = recast<uint4>(T.deg);
         for (int32_t i = l; i < a.n_leaf / 8; i += kWave) dst[i] = src[i];
-        for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = a.tree0[i];
+        for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = gptr(a.tree0)[i];
         if (OWN) {
             for (int32_t x = l; x < 2 * n; x += kWave) {
                 float s = 1.0f;
-                if (x < n) { if (a.r0) s = a.r0[x]; }
-                else if (a.c0) s = a.c0[x - n];
+                if (x < n) { if (T.r0) s = T.r0[x]; }
+                else if (T.c0) s = T.c0[x - n];
                 T.rec[x] = Rec{s, 0};
             }
         }
         if (DM) {
             for (int32_t i = l; i < (a.A.m + 31) / 32; i += kWave) T.rem[i] = 0;
             for (int32_t i = l; i < n; i += kWave) {
-                T.mate_r[i] = a.mate0_r ? a.mate0_r[i] : -1;
-                T.mate_c[i] = a.mate0_c ? a.mate0_c[i] : -1;
+                T.mate_r[i] = a.mate0_r ? gptr(a.mate0_r)[i] : -1;
+                T.mate_c[i] = a.mate0_c ? gptr(a.mate0_c)[i] : -1;
             }
         }
         if (path)
@@ -938,8 +953,8 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
                 int32_t L = 0;
                 if (kc > 1) {
-                    const float r0r = a.r0 ? a.r0[cand ? rho_c : 0] : 1.0f;
-                    const float c0g = a.c0 ? a.c0[cand ? gam_c - n : 0] : 1.0f;
+                    const float r0r = T.r0 ? T.r0[cand ? rho_c : 0] : 1.0f;
+                    const float c0g = T.c0 ? T.c0[cand ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
                     candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc);
@@ -1005,7 +1020,7 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                             const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
                             float x[8];
                             learned_features(x, v_row ? deg_v : cd, v_row ? cd : deg_v,
-                                             a.r0 ? a.r0[rho_c] : 1.0f, a.c0 ? a.c0[gam_c - n] : 1.0f, t, n, v_row,
+                                             T.r0 ? T.r0[rho_c] : 1.0f, T.c0 ? T.c0[gam_c - n] : 1.0f, t, n, v_row,
                                              su, c2);
                             float4 *xo = reinterpret_cast<float4 *>(a.rec_x + r * 8);
                             xo[0] = make_float4(x[0], x[1], x[2], x[3]);
@@ -1078,8 +1093,8 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                         c0 = dy != kRetired && !T.removed(e);
                     }
                     const int32_t rho_c = v_row ? v : y, gam_c = v_row ? y : v;
-                    const float r0r = a.r0 ? a.r0[c0 ? rho_c : 0] : 1.0f;
-                    const float c0g = a.c0 ? a.c0[c0 ? gam_c - n : 0] : 1.0f;
+                    const float r0r = T.r0 ? T.r0[c0 ? rho_c : 0] : 1.0f;
+                    const float c0g = T.c0 ? T.c0[c0 ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
                     int32_t yub = 0, yue = 0;
@@ -1169,6 +1184,17 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
             alive = false;
             break;
         }
+        // u's leaf group needs a new minimum after the step when u is that
+        // minimum (and the group is not v's, refreshed from the selection's
+        // leaves): read its leaves now, before this step's stores, so the
+        // refresh needs no memory round trip. Stale values are harmless:
+        // the step only lowers degrees (the new ones are known) and retires
+        // v and u (masked).
+        const int32_t gu = u >> 8;
+        const uint32_t l1u_before = T.level(0)[gu];
+        const bool refresh_u = gu != gsel && d_u <= l1u_before;
+        uint2 uleaves = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        if (refresh_u && gsel >= 0) uleaves = recast<const uint2>(T.deg + 256 * gu)[l];
 
         // ---- importance correction X <- X * B_vu / q(u|v), extended exponent
         {
@@ -1237,8 +1263,6 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
                 kb += __popcll(msk);
             }
         }
-        const int32_t gu = u >> 8;
-        const uint32_t l1u_before = T.level(0)[gu];
         wave_fence();
 
         // ---- B^(t+1) = B^(t) \ {v,u}: retire both, lower their neighbours
@@ -1248,37 +1272,28 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
             if (OWN) { T.rec[v].s = -1.0f; T.rec[u].s = -1.0f; }
         }
         uint32_t dec_min_g = 0xFFFFFFFFu;  // lowest new degree inside v's leaf group
+        uint32_t dec_min_u = 0xFFFFFFFFu;  // ... and inside u's
+        auto lower = [&](int32_t y, uint32_t nd) {
+            T.deg[y] = (uint16_t)nd;
+            T.tree_lower(y, nd);
+            if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+            if ((y >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
+        };
         if (fast_v) {
-            if (cand && cy != u) {
-                const uint32_t nd = cd - 1u;
-                T.deg[cy] = (uint16_t)nd;
-                T.tree_lower(cy, nd);
-                if ((cy >> 8) == gsel) dec_min_g = nd;
-            }
+            if (cand && cy != u) lower(cy, cd - 1u);
         } else {
             for (int32_t idx = l; idx < kc; idx += kWave) {
                 const int32_t y = T.lst_a[idx];
                 if (y == u) continue;
-                const uint32_t nd = (uint32_t)T.deg[y] - 1u;
-                T.deg[y] = (uint16_t)nd;
-                T.tree_lower(y, nd);
-                if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+                lower(y, (uint32_t)T.deg[y] - 1u);
             }
         }
         if (fast_u) {
-            if (take) {
-                const uint32_t nd = bd - 1u;
-                T.deg[by] = (uint16_t)nd;
-                T.tree_lower(by, nd);
-                if ((by >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
-            }
+            if (take) lower(by, bd - 1u);
         } else {
             for (int32_t idx = l; idx < kb; idx += kWave) {
                 const int32_t y = T.lst_b[idx];
-                const uint32_t nd = (uint32_t)T.deg[y] - 1u;
-                T.deg[y] = (uint16_t)nd;
-                T.tree_lower(y, nd);
-                if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+                lower(y, (uint32_t)T.deg[y] - 1u);
             }
         }
         work.scan += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
@@ -1298,10 +1313,24 @@ __device__ __forceinline__ void run_trajectory(const TrajArgs &a, const Traj<Own
             if (l == 0) T.level(0)[gsel] = mm;
             wave_fence();
             T.refresh_upper(gsel);
+            if (refresh_u) {
+                const int32_t ub_id = 256 * gu + 4 * l;
+                uint32_t e0 = uleaves.x & 0xFFFFu, e1 = uleaves.x >> 16, e2 = uleaves.y & 0xFFFFu,
+                         e3 = uleaves.y >> 16;
+                if (ub_id == u) e0 = 0xFFFFu;
+                if (ub_id + 1 == u) e1 = 0xFFFFu;
+                if (ub_id + 2 == u) e2 = 0xFFFFu;
+                if (ub_id + 3 == u) e3 = 0xFFFFu;
+                uint32_t mu = min(min(e0, e1), min(e2, e3));
+                mu = wave_min_u32(min(mu, dec_min_u));
+                if (l == 0) T.level(0)[gu] = mu;
+                wave_fence();
+                T.refresh_upper(gu);
+            }
         } else {
             T.tree_refresh(v);
+            if (refresh_u) T.tree_refresh(u);
         }
-        if (gu != gsel && d_u <= l1u_before) T.tree_refresh(u);
         steps = t + 1;
         track = track * z;
         if (t + 1 >= n) break;
@@ -1405,7 +1434,7 @@ constexpr int kMlpBlockBytes = ((int)sizeof(LearnedLds) + 15) / 16 * 16;
 template <int SK, bool DM, bool WT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((SK == kSkNone || !DM) ? 4 : 1, 8)))
 traj_kernel(const BatchArgs *__restrict__ bp) {
-    const BatchArgs &B = *bp;
+    const PE_G BatchArgs &B = *gptr(bp);
     extern __shared__ __align__(16) char smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
     // block: [network weights (learned)] then per wave [tree | network tiles | state]
@@ -1429,18 +1458,24 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     Work work;
     for (;;) {
         uint32_t q = 0;
-        if (lane_id() == 0) q = atomicAdd(B.work_next, 1u);
+        if (lane_id() == 0) q = atomicAdd(gptr(B.work_next), 1u);
         q = read_lane(q, 0);
         if ((int64_t)q >= B.total) break;
         // matrix of item q: last i with item_off[i] <= q
         int32_t lo = 0, hi = B.count - 1;
         while (lo < hi) {
             const int32_t mid = (lo + hi + 1) >> 1;
-            if (B.item_off[mid] <= (int64_t)q) lo = mid; else hi = mid - 1;
+            if (gptr(B.item_off)[mid] <= (int64_t)q) lo = mid; else hi = mid - 1;
         }
-        const TrajArgs &a = B.mats[B.order[lo]];
-        const Traj<OwnRC<SK>::value, DM, WT> T(a, a.lds_tier ? lds_state : hbm_state, tree);
-        run_trajectory<SK, DM, WT>(a, T, (int64_t)q - B.item_off[lo], work, lrn, mlps);
+        const PE_G TrajArgs &a = gptr(B.mats)[gptr(B.order)[lo]];
+        const int64_t k = (int64_t)q - gptr(B.item_off)[lo];
+        if (a.lds_tier) {
+            const Traj<OwnRC<SK>::value, DM, WT, kAsLds> T(a, lds_state, tree);
+            run_trajectory<SK, DM, WT, kAsLds>(a, T, k, work, lrn, mlps);
+        } else {
+            const Traj<OwnRC<SK>::value, DM, WT, kAsGlobal> T(a, hbm_state, tree);
+            run_trajectory<SK, DM, WT, kAsGlobal>(a, T, k, work, lrn, mlps);
+        }
     }
     if (lane_id() == 0 && B.work_totals) {
         atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);

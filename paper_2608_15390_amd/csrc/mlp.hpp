@@ -66,18 +66,23 @@ __device__ __forceinline__ int w2_index(int r, int c) {
     return ((ks * 4 + nt) * 64 + lane) * 4 + (r & 3);
 }
 
+// GRID (inference on the grid, parameters already snapped to k/64): W1, b1
+// and b2 are staged times 64, so that layers 1 and 2 produce 64 z directly
+// and the activations are the grid integers k (see mlp_tile_forward).
+template <bool GRID = false>
 __device__ void stage_weights(MlpLds *s, const float *P) {
+    const float g = GRID ? 64.0f : 1.0f;
     for (int i = threadIdx.x; i < kIn * kH; i += blockDim.x) {
         const int j = i & 3, lane = (i >> 2) & 31, nt = i >> 7;
-        s->w1[i] = to_bf16(P[kOffW1 + (4 * (lane >> 4) + j) * kH + 16 * nt + (lane & 15)]);
+        s->w1[i] = to_bf16(g * P[kOffW1 + (4 * (lane >> 4) + j) * kH + 16 * nt + (lane & 15)]);
     }
     for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
         const int r = i >> 6, c = i & 63;
         s->w2[w2_index(r, c)] = to_bf16(P[kOffW2 + i]);
     }
     for (int i = threadIdx.x; i < kH; i += blockDim.x) {
-        s->b1[i] = P[kOffB1 + i];
-        s->b2[i] = P[kOffB2 + i];
+        s->b1[i] = g * P[kOffB1 + i];
+        s->b2[i] = g * P[kOffB2 + i];
         s->w3[i] = P[kOffW3 + i];
     }
     if (threadIdx.x == 0) s->b3 = P[kOffB3];
@@ -91,7 +96,14 @@ struct TileLds {
 // Forward of one tile.  `xa` is this lane's A operand of the feature tile
 // (record l % 16, features 4 (l / 16) .. +3; features 8..15 are zero).
 // QUANT: re-quantise the ReLU outputs onto the 1/64 grid [0, 255/64]
-// (inference); otherwise plain ReLU (training).  Outputs in D layout:
+// (inference, weights staged with GRID); otherwise plain ReLU (training).
+// On the grid the tile carries everything times 64: with W1, b1 and b2
+// staged times 64, layer 1 yields 64 z1 and an activation is the integer
+// k = med3(rint(64 z1), 0, 255) (exact in bf16); layer 2 on those integers
+// with the unscaled W2 again yields 64 z2; layer 3 sums k w3 and scales by
+// 1/64 at the end. Every product and partial sum is exact in binary32 (grid
+// values, at most 64 terms), so each value equals the unscaled one times 64
+// bit for bit and the logits are identical.  Outputs in D layout:
 // z1[nt], z2[nt] (pre-activations, column 16 nt + l % 16, rows
 // 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (complete in the
 // last lane of each 16-lane group, l % 16 == 15).
@@ -106,7 +118,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
     // ReLU, and on the inference grid: snap to k/64, k in [0, 255] (one
     // round and one median); such values are exact in bf16
     auto act = [](float z) -> float {
-        if (QUANT) return __builtin_amdgcn_fmed3f(rintf(z * 64.0f), 0.0f, 255.0f) * (1.0f / 64.0f);
+        if (QUANT) return __builtin_amdgcn_fmed3f(rintf(z), 0.0f, 255.0f);
         return z > 0.0f ? z : 0.0f;
     };
     auto act_bf16 = [&](float z) -> short {
@@ -161,7 +173,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         v = fadd(v, dpp<kRowShr2>(0u, v));
         v = fadd(v, dpp<kRowShr4>(0u, v));
         v = fadd(v, dpp<kRowShr8>(0u, v));
-        logit[j] = __uint_as_float(v) + W->b3;
+        logit[j] = (QUANT ? __uint_as_float(v) * (1.0f / 64.0f) : __uint_as_float(v)) + W->b3;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }

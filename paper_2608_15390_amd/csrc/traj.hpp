@@ -1442,7 +1442,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     MlpLds *mlpw = &lrn->net;
     char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
     if (SK == kSkLearned) {
-        stage_weights(mlpw, B.mlp);
+        stage_weights<true>(mlpw, B.mlp);
         for (int i = threadIdx.x; i < kEtabLds; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
         __syncthreads();
     }

@@ -237,11 +237,12 @@ struct Traj {
     // minimum can be refreshed from registers after the step, and the
     // selected vertex's list bounds, loaded for the whole group together
     // with its leaves (one memory round trip instead of two).
-    __device__ bool select_min(int32_t &vsel, int32_t &gsel, uint2 &leaves, int32_t &vb, int32_t &ve) const {
+    __device__ bool select_min(int32_t &vsel, int32_t &gsel, uint2 &leaves, int32_t &vb, int32_t &ve,
+                               uint32_t &m) const {
         const int l = lane_id();
         const int top = a.tree.levels - 1;
         uint32_t v = l < a.tree.size[top] ? level(top)[l] : 0xFFFFFFFFu;
-        const uint32_t m = wave_min_u32(v);
+        m = wave_min_u32(v);
         uint64_t hit = ballot(v == m);
         int32_t g = __ffsll((unsigned long long)hit) - 1;
         for (int k = top - 1; k >= 0 && hit; --k) {
@@ -905,11 +906,12 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         // ---- choose the vertex
         int32_t v = -1, gsel = -1;
         int32_t vb = 0, ve = 0;
+        uint32_t m_sel = 0;  // the minimum degree at selection (v's group minimum)
         uint2 gleaves = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
         if (a.vertex_rule == 1) {
             v = t;
             T.list(v, vb, ve);
-        } else if (!T.select_min(v, gsel, gleaves, vb, ve)) {
+        } else if (!T.select_min(v, gsel, gleaves, vb, ve, m_sel)) {
             v = -1;
         }
         if (v < 0 || v >= 2 * n) {  // internal inconsistency: report, never index
@@ -1312,7 +1314,10 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             mm = wave_min_u32(min(mm, dec_min_g));
             if (l == 0) T.level(0)[gsel] = mm;
             wave_fence();
-            T.refresh_upper(gsel);
+            // the upper levels hold every lower value already (atomic
+            // minima of the decrements); they change only if the group's
+            // minimum rose above the selected degree
+            if (mm > m_sel) T.refresh_upper(gsel);
             if (refresh_u) {
                 const int32_t ub_id = 256 * gu + 4 * l;
                 uint32_t e0 = uleaves.x & 0xFFFFu, e1 = uleaves.x >> 16, e2 = uleaves.y & 0xFFFFu,
@@ -1325,7 +1330,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 mu = wave_min_u32(min(mu, dec_min_u));
                 if (l == 0) T.level(0)[gu] = mu;
                 wave_fence();
-                T.refresh_upper(gu);
+                if (mu > d_u) T.refresh_upper(gu);
             }
         } else {
             T.tree_refresh(v);
@@ -1335,7 +1340,12 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         track = track * z;
         if (t + 1 >= n) break;
 
-        if (T.global_min() == 0) { alive = false; break; }  // child dead end
+        // child dead end. Under minimum-degree selection without inner SK or
+        // DM nothing runs before the next selection, which then picks a
+        // vertex of degree 0 and stops the trajectory at the same point with
+        // the same counters, so the check is left to it.
+        const bool next_select_checks = (SK == kSkNone || SK == kSkLearned) && !DM && a.vertex_rule != 1;
+        if (!next_select_checks && T.global_min() == 0) { alive = false; break; }
 
         // ---- P_DM: support filtering of the child
         if (DM) {

@@ -147,6 +147,12 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) { return read_lane(wave_incl_scan_u64(x), kWave - 1); }
 
+// 32-bit inclusive prefix sum, for values whose total over the wave fits
+// (integer proposal weights are at most 2^24 + 1, so 64 of them do)
+__device__ __forceinline__ uint32_t wave_incl_scan_add_u32(uint32_t x) {
+    return wave_scan_u32(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
 __device__ __forceinline__ int wave_sum_i32(int x) {
     const uint32_t r = wave_scan_u32((uint32_t)x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
     return (int)read_lane(r, kWave - 1);

@@ -83,6 +83,11 @@ __device__ __forceinline__ uint64_t row_incl_scan_u64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint64_t row_sum_u64(uint64_t x) { return row_bcast64<15>(row_incl_scan_u64(x)); }
+// 32-bit inclusive prefix sum within each row (16 proposal weights of at
+// most 2^24 + 1 fit)
+__device__ __forceinline__ uint32_t row_incl_scan_add_u32(uint32_t x) {
+    return row_scan_u32(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
 __device__ __forceinline__ int32_t row_excl_scan_i32(int32_t x, int32_t &total) {
     const uint32_t incl = row_scan_u32((uint32_t)x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
     total = (int32_t)row_bcast<15>(incl);
@@ -329,8 +334,8 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                     const float smax = row_max_f32((cand && s > 0.0f) ? s : 0.0f);
                     const bool uniform = !(smax > 0.0f) || __builtin_isinf(smax);
                     const uint64_t w = cand ? scaled_weight(s, smax, uniform, kc) : 0ull;
-                    const uint64_t incl = row_incl_scan_u64(w);
-                    Wt = row_bcast64<15>(incl);
+                    const uint64_t incl = row_incl_scan_add_u32((uint32_t)w);
+                    Wt = row_bcast<15>((uint32_t)incl);
                     const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), Wt, a.seed, k,
                                                             a.b, (uint32_t)t)
                                               : 0ull;
@@ -381,7 +386,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                             T.entry<WT>(v_row, p, y, bvv);
                             if (T.deg[y] != kRetired) w = weight_of(y, bvv);
                         }
-                        Wt += row_sum_u64(w);
+                        Wt += row_bcast<15>(row_incl_scan_add_u32((uint32_t)w));
                     }
                     const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), Wt, a.seed, k,
                                                             a.b, (uint32_t)t)
@@ -397,7 +402,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                             T.entry<WT>(v_row, p, y, bvv);
                             if (T.deg[y] != kRetired) w = weight_of(y, bvv);
                         }
-                        const uint64_t incl = row_incl_scan_u64(w) + pre;
+                        const uint64_t incl = row_incl_scan_add_u32((uint32_t)w) + pre;
                         const uint32_t hm = row_bits(ballot(w != 0 && incl > j && incl - w <= j));
                         if (hm) {
                             const int src = __ffs(hm) - 1;

@@ -526,7 +526,6 @@ __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total)
 template <class TT>
 __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
                                                    Work &work) {
-    const auto &a = T.a;
     const int l = lane_id();
     const int32_t n = T.n;
     const int32_t mark = t + 1;
@@ -708,28 +707,74 @@ __device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int3
 template <int SK>
 struct OwnRC { static constexpr bool value = SK == kSkFixed || SK == kSkAdaptive || SK == kSkLocal; };
 
-// features of the candidate edge of Eq. (q) for the learned proposal (see
-// the definition in the oracle): exact operations only
-__device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uint32_t deg_gam, float r0_rho,
-                                                 float c0_gam, int32_t t, int32_t n, bool v_row, uint64_t s_u,
-                                                 int32_t c2_u) {
-    auto q64 = [](double y) -> float {
-        double k = rint(y * 64.0);
-        k = k < -256.0 ? -256.0 : (k > 255.0 ? 255.0 : k);
-        return (float)(k / 64.0);
-    };
-    auto plog2 = [](double s) -> double {
+// Features of the candidate edge of Eq. (q) for the learned proposal. The
+// definition (the oracle's) is FP64: Q(y) = clamp(rint(64 y), -256, 255) / 64
+// and plog2(s) = e - 2 + 2m with (m, e) = frexp(s). The grid integers are
+// formed here with integer operations that give the same values:
+// * for a positive normal binary32 s = 2^(E-127) (1 + M/2^23),
+//   plog2(s) = E - 127 + M/2^23, so 64 plog2(s)/4 = (bits >> 19) - 2032
+//   plus the low 19 bits over 2^19, rounded half to even. (In FP64 the sum
+//   e - 2 + 2m is exact to 2^-42 in these units, far finer than the 2^-19
+//   steps of a binary32 input, so no rounding of the definition differs.)
+//   Zero, subnormal and other inputs take the FP64 definition;
+// * for an integer S >= 1 with 2^p <= S < 2^(p+1), 16 plog2(S) = 16 p +
+//   16 S / 2^p - 16, exact in integers; S / 2^20 shifts it by -320;
+// * t/n's grid integer rint(64 t / n) is kept incrementally by the caller
+//   (k4); the rational 64 t / n is a tie exactly when the FP64 quotient is.
+__device__ __forceinline__ int32_t q_clamp(int32_t k) { return k < -256 ? -256 : (k > 255 ? 255 : k); }
+
+__device__ __forceinline__ float q64_plog2_quarter(float s) {
+    const uint32_t b = __float_as_uint(s);
+    int32_t k;
+    if (b >= 0x00800000u && b < 0x7F800000u) {
+        const uint32_t q = b >> 19, r = b & 0x7FFFFu;
+        const uint32_t up = (r > 0x40000u || (r == 0x40000u && (q & 1u))) ? 1u : 0u;
+        k = (int32_t)(q + up) - 2032;
+    } else {
         int e;
-        const double m = frexp(s, &e);
-        return (double)e - 2.0 + 2.0 * m;
-    };
+        const double m = frexp((double)s, &e);
+        const double y = rint(((double)e - 2.0 + 2.0 * m) / 4.0 * 64.0);
+        k = y < -256.0 ? -256 : (y > 255.0 ? 255 : (int32_t)y);
+    }
+    return (float)q_clamp(k) * (1.0f / 64.0f);
+}
+
+// Q(plog2(S / 2^20) / 4) for the integer S (at most 2^53)
+__device__ __forceinline__ float q64_plog2_quarter_fixed20(uint64_t S) {
+    int32_t k = -32;  // plog2(0) = -2
+    if (S != 0) {
+        const int p = 63 - __builtin_clzll(S);
+        const uint64_t t16 = S << 4;
+        const uint32_t q = (uint32_t)(t16 >> p);  // 16 .. 31
+        uint32_t up = 0;
+        if (p > 0) {
+            const uint64_t r = t16 & ((1ull << p) - 1ull), half = 1ull << (p - 1);
+            up = (r > half || (r == half && (q & 1u))) ? 1u : 0u;
+        }
+        k = 16 * p + (int32_t)(q + up) - 16 - 320;
+    }
+    return (float)q_clamp(k) * (1.0f / 64.0f);
+}
+
+// k4 = rint(64 t / n) (ties to even), advanced from step t - 1 to step t
+__device__ __forceinline__ int32_t advance_t_grid(int32_t k4, int32_t t, int32_t n) {
+    for (;;) {
+        const int64_t lhs = 128 * (int64_t)t, rhs = (2 * (int64_t)k4 + 1) * n;
+        if (lhs > rhs || (lhs == rhs && (k4 & 1))) ++k4;
+        else return k4;
+    }
+}
+
+__device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uint32_t deg_gam, float r0_rho,
+                                                 float c0_gam, int32_t k4, bool v_row, uint64_t s_u,
+                                                 int32_t c2_u) {
     x[0] = (float)(deg_rho < 255u ? deg_rho : 255u) / 64.0f;
     x[1] = (float)(deg_gam < 255u ? deg_gam : 255u) / 64.0f;
-    x[2] = q64(plog2((double)r0_rho) / 4.0);
-    x[3] = q64(plog2((double)c0_gam) / 4.0);
-    x[4] = q64((double)t / (double)n);
+    x[2] = q64_plog2_quarter(r0_rho);
+    x[3] = q64_plog2_quarter(c0_gam);
+    x[4] = (float)q_clamp(k4) * (1.0f / 64.0f);
     x[5] = v_row ? 1.0f : 0.0f;
-    x[6] = q64(plog2((double)s_u * (1.0 / 1048576.0)) / 4.0);
+    x[6] = q64_plog2_quarter_fixed20(s_u);
     x[7] = (float)(c2_u < 255 ? c2_u : 255) / 64.0f;
 }
 
@@ -822,11 +867,11 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, i
 // the layer-1 activations pass through LDS).  Lanes without a candidate
 // return 0.
 __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uint32_t deg_rho,
-                                  uint32_t deg_gam, float r0_rho, float c0_gam, int32_t t, int32_t n,
+                                  uint32_t deg_gam, float r0_rho, float c0_gam, int32_t k4,
                                   bool v_row, uint64_t s_u, int32_t c2_u, int32_t chunk_len) {
     const int l = lane_id();
     float x[8];
-    learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, t, n, v_row, s_u, c2_u);
+    learned_features(x, deg_rho, deg_gam, r0_rho, c0_gam, k4, v_row, s_u, c2_u);
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = cand ? x[k] : 0.0f;
     const int grp = l >> 4;  // A-operand features 4 grp .. 4 grp + 3 (grp < 2)
@@ -902,7 +947,9 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
     int32_t steps = 0, n_dm = 0, n_sweeps = 0, n_local = 0;
     bool alive = a.ok0 != 0;
 
+    int32_t k4 = 0;  // learned feature x4: rint(64 t / n)
     for (int32_t t = 0; alive && t < n; ++t) {
+        k4 = advance_t_grid(k4, t, n);
         // ---- choose the vertex
         int32_t v = -1, gsel = -1;
         int32_t vb = 0, ve = 0;
@@ -961,7 +1008,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     int32_t c2;
                     candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc);
                     L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
-                                       t, n, v_row, su, c2, ve - vb);
+                                       k4, v_row, su, c2, ve - vb);
                     work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
                 }
                 const int32_t lmx = wave_max_i32(cand ? L : -2147483647);
@@ -970,7 +1017,8 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     const int32_t d = lmx - L;
                     E = d < kEtabLds ? (int64_t)etab[d] : 0;
                 }
-                const int64_t S = (int64_t)wave_sum_u64((uint64_t)E);
+                // at most 2^24 per lane: the 64-lane total fits 32 bits
+                const int64_t S = (int64_t)read_lane(wave_incl_scan_add_u32((uint32_t)E), kWave - 1);
                 if (cand) {
                     if (kc == 1) w = 1;
                     else {
@@ -1022,7 +1070,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                             const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
                             float x[8];
                             learned_features(x, v_row ? deg_v : cd, v_row ? cd : deg_v,
-                                             T.r0 ? T.r0[rho_c] : 1.0f, T.c0 ? T.c0[gam_c - n] : 1.0f, t, n, v_row,
+                                             T.r0 ? T.r0[rho_c] : 1.0f, T.c0 ? T.c0[gam_c - n] : 1.0f, k4, v_row,
                                              su, c2);
                             float4 *xo = reinterpret_cast<float4 *>(a.rec_x + r * 8);
                             xo[0] = make_float4(x[0], x[1], x[2], x[3]);
@@ -1040,7 +1088,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     }
                 }
             }
-            const uint64_t incl = wave_incl_scan_u64(w);
+            const uint64_t incl = wave_incl_scan_add_u32((uint32_t)w);
             W = read_lane(incl, kWave - 1);
             const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), W, a.seed, k, a.b, (uint32_t)t) : 0ull;
             const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
@@ -1104,7 +1152,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     NbrCache lnc;
                     candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc);
                     const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
-                                                     v_row ? dy : (uint32_t)kc, r0r, c0g, t, n, v_row, su, c2,
+                                                     v_row ? dy : (uint32_t)kc, r0r, c0g, k4, v_row, su, c2,
                                                      min(kWave, ve - base));
                     work.mlp_tiles += (uint64_t)((min(kWave, ve - base) + 15) / 16);
                     const uint64_t msk = ballot(c0);
@@ -1149,7 +1197,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 const uint64_t msk = ballot(c0);
                 if (c0) w = weight_of(y, bv, cbase + rank_below(msk));
                 cbase += __popcll(msk);
-                W += wave_sum_u64(w);
+                W += read_lane(wave_incl_scan_add_u32((uint32_t)w), kWave - 1);
             }
             const uint64_t j = kc > 1 ? lemire_from(rand64(a.seed, k, a.b, (uint32_t)t, 0u), W, a.seed, k, a.b, (uint32_t)t) : 0ull;
             uint64_t pre = 0;
@@ -1167,7 +1215,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 const uint64_t msk = ballot(c0);
                 if (c0) w = weight_of(y, bv, cbase + rank_below(msk));
                 cbase += __popcll(msk);
-                const uint64_t incl = wave_incl_scan_u64(w) + pre;
+                const uint64_t incl = wave_incl_scan_add_u32((uint32_t)w) + pre;
                 const uint64_t hm = ballot(w != 0 && incl > j && incl - w <= j);
                 if (hm) {
                     const int src = __ffsll((unsigned long long)hm) - 1;

@@ -513,6 +513,28 @@ __device__ __forceinline__ int owner_lane(int32_t f, int32_t off) {
     return lo;
 }
 
+// The same owner for every flattened position base + lane at once, when an
+// LDS array of kWave ints is free: each list that starts inside the pass
+// writes its lane at its start, and an inclusive max-scan carries it to the
+// positions that follow (carry: the owner at the end of the previous pass).
+// Lanes with empty lists never own a position, so the largest lane with a
+// start at or before a position is its owner, as in owner_lane.
+__device__ __forceinline__ int owners_in_pass(int32_t off, int32_t len, int32_t base, int32_t &carry,
+                                              int32_t *scratch) {
+    const int l = lane_id();
+    scratch[l] = -1;
+    wave_fence();
+    const int32_t s = off - base;
+    if (len > 0 && s >= 0 && s < kWave) scratch[s] = l;
+    wave_fence();
+    uint32_t v = (uint32_t)scratch[l];
+    v = wave_scan_u32(v, 0x80000000u, [](uint32_t x, uint32_t y) { return (int32_t)y > (int32_t)x ? y : x; });
+    int32_t o = (int32_t)v > carry ? (int32_t)v : carry;
+    carry = read_lane(o, kWave - 1);
+    wave_fence();
+    return o;
+}
+
 __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total) {
     const uint32_t incl = wave_scan_u32((uint32_t)x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
     total = (int32_t)read_lane(incl, kWave - 1);
@@ -796,9 +818,10 @@ struct NbrCache {
 // candidates' lists are flattened over the wave (64 entries per pass) and
 // summed per owner with a segmented scan; integer sums, so the result does
 // not depend on the order.
+// scratch: kWave ints of the wave's LDS for the owner search, or nullptr
 template <class TT>
 __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, int32_t ue, int32_t v,
-                                uint64_t &s_u, int32_t &c2_u, NbrCache &nc) {
+                                uint64_t &s_u, int32_t &c2_u, NbrCache &nc, int32_t *scratch) {
     const int l = lane_id();
     const bool u_row = u < T.n;
     const int32_t len = cand ? ue - ub : 0;
@@ -810,10 +833,18 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, i
     nc.off = off;
     nc.ub = ub;
     nc.len = len;
+    int32_t carry = -1;
     for (int32_t base = 0; base < total; base += kWave) {
         const int32_t f = base + l;
         const bool valid = f < total;
-        const int own = owner_lane(valid ? f : total - 1, off);
+        int own;
+        if (scratch) {
+            // past the end (f >= total) this is the last list's lane, as below
+            own = owners_in_pass(off, len, base, carry, scratch);
+            own = own < 0 ? 0 : own;
+        } else {
+            own = owner_lane(valid ? f : total - 1, off);
+        }
         const int32_t o_off = __shfl(off, own);
         const int32_t o_ub = __shfl(ub, own);
         const bool o_row = __shfl((int)u_row, own) != 0;
@@ -1006,7 +1037,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     const float c0g = T.c0 ? T.c0[cand ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
-                    candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc);
+                    candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc, reinterpret_cast<int32_t *>(mlps->h));
                     L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
                                        k4, v_row, su, c2, ve - vb);
                     work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
@@ -1049,7 +1080,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     int32_t rub = 0, rue = 0;
                     if (cand) T.list(cy, rub, rue);
                     NbrCache rnc;
-                    candidate_stats(T, cand, cy, rub, rue, v, su, c2, rnc);
+                    candidate_stats(T, cand, cy, rub, rue, v, su, c2, rnc, nullptr);
                     unsigned long long old = 0;
                     if (l == 0) {
                         const unsigned long long cur = __hip_atomic_load(a.rec_counter, __ATOMIC_RELAXED,
@@ -1150,7 +1181,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     int32_t yub = 0, yue = 0;
                     if (c0) T.list(y, yub, yue);
                     NbrCache lnc;
-                    candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc);
+                    candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc, reinterpret_cast<int32_t *>(mlps->h));
                     const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
                                                      v_row ? dy : (uint32_t)kc, r0r, c0g, k4, v_row, su, c2,
                                                      min(kWave, ve - base));

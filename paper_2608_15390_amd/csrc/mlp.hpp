@@ -68,7 +68,7 @@ __device__ __forceinline__ int w2_index(int r, int c) {
 
 // GRID (inference on the grid, parameters already snapped to k/64): W1, b1
 // and b2 are staged times 64, so that layers 1 and 2 produce 64 z directly
-// and the activations are the grid integers k (see mlp_tile_forward).
+// and the activations are the grid integers k (see mlp_tile_logit_grid).
 template <bool GRID = false>
 __device__ void stage_weights(MlpLds *s, const float *P) {
     const float g = GRID ? 64.0f : 1.0f;
@@ -93,38 +93,21 @@ struct TileLds {
     short h[16 * kH];
 };
 
-// Forward of one tile.  `xa` is this lane's A operand of the feature tile
-// (record l % 16, features 4 (l / 16) .. +3; features 8..15 are zero).
-// QUANT: re-quantise the ReLU outputs onto the 1/64 grid [0, 255/64]
-// (inference, weights staged with GRID); otherwise plain ReLU (training).
-// On the grid the tile carries everything times 64: with W1, b1 and b2
-// staged times 64, layer 1 yields 64 z1 and an activation is the integer
-// k = med3(rint(64 z1), 0, 255) (exact in bf16); layer 2 on those integers
-// with the unscaled W2 again yields 64 z2; layer 3 sums k w3 and scales by
-// 1/64 at the end. Every product and partial sum is exact in binary32 (grid
-// values, at most 64 terms), so each value equals the unscaled one times 64
-// bit for bit and the logits are identical.  Outputs in D layout:
-// z1[nt], z2[nt] (pre-activations, column 16 nt + l % 16, rows
-// 4 (l / 16) + j) and the logits of rows 4 (l / 16) + j (complete in the
-// last lane of each 16-lane group, l % 16 == 15).
+// Forward of one tile of the float network (training).  `xa` is this
+// lane's A operand of the feature tile (record l % 16, features
+// 4 (l / 16) .. +3; features 8..15 are zero).  Outputs in D layout: z1[nt],
+// z2[nt] (pre-activations, column 16 nt + l % 16, rows 4 (l / 16) + j) and
+// the logits of rows 4 (l / 16) + j (complete in the last lane of each
+// 16-lane group, l % 16 == 15).
 // four consecutive bf16 operands (8-byte aligned)
 __device__ __forceinline__ bf16x4 load_b4(const short *p) { return *reinterpret_cast<const bf16x4 *>(p); }
 
-template <bool QUANT>
 __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf16x4 xa, f32x4 z1[4],
                                                  f32x4 z2[4], float logit[4]) {
     const int l = lane_id();
     const int c0 = l % 16, r0 = 4 * (l / 16);
-    // ReLU, and on the inference grid: snap to k/64, k in [0, 255] (one
-    // round and one median); such values are exact in bf16
-    auto act = [](float z) -> float {
-        if (QUANT) return __builtin_amdgcn_fmed3f(rintf(z), 0.0f, 255.0f);
-        return z > 0.0f ? z : 0.0f;
-    };
-    auto act_bf16 = [&](float z) -> short {
-        const float h = act(z);
-        return QUANT ? (short)(__float_as_uint(h) >> 16) : to_bf16(h);
-    };
+    auto act = [](float z) -> float { return z > 0.0f ? z : 0.0f; };
+    auto act_bf16 = [&](float z) -> short { return to_bf16(act(z)); };
     // layer 1: [16 x 16] x [16 x 64], the bias as the accumulator's start
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -155,12 +138,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         }
         const float w3 = W->w3[16 * nt + c0];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            // on the grid every product and partial sum is exact, so a fused
-            // multiply-add rounds nothing
-            if (QUANT) part[j] = __builtin_fmaf(act(acc[j]), w3, part[j]);
-            else part[j] = part[j] + act(acc[j]) * w3;
-        }
+        for (int j = 0; j < 4; ++j) part[j] = part[j] + act(acc[j]) * w3;
         z2[nt] = acc;
     }
     // layer 3: sum the 64 columns over the 16 lanes of each row group (a
@@ -173,9 +151,60 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds *W, TileLds *T, bf
         v = fadd(v, dpp<kRowShr2>(0u, v));
         v = fadd(v, dpp<kRowShr4>(0u, v));
         v = fadd(v, dpp<kRowShr8>(0u, v));
-        logit[j] = (QUANT ? __uint_as_float(v) * (1.0f / 64.0f) : __uint_as_float(v)) + W->b3;
+        logit[j] = __uint_as_float(v) + W->b3;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// Inference on the grid (weights staged with GRID), network transposed:
+// each layer computes W^T times the transposed activations, so the weights
+// are the A operand and the activations the B operand. The B-layout staging
+// of W is exactly the A layout of W^T, and the feature tile xb is the same
+// operand as xa above (record l % 16, features 4 (l / 16) + j). One tile's
+// result in D layout (rows 4 (l / 16) + j, column l % 16) is the B operand
+// of the next layer's K-step as it stands, so the activations stay in
+// registers. Each lane ends with the logit of record l % 16: the four rows
+// hold partial sums over complementary hidden units, added across rows by
+// two lane-swap steps.
+// The tile carries everything times 64: with W1, b1 and b2 staged times 64,
+// layer 1 yields 64 z1 and an activation is the grid integer
+// k = med3(rint(64 z1), 0, 255) (exact in bf16); layer 2 on those integers
+// with the unscaled W2 yields 64 z2; layer 3 sums k w3 and scales by 1/64
+// at the end. Every product and partial sum is a grid value with at most
+// 64 terms, exact in binary32, so neither the scaling nor the order of the
+// sums changes a logit: it is the exact value of the snapped network.
+__device__ __forceinline__ float mlp_tile_logit_grid(const MlpLds *W, bf16x4 xb) {
+    const int l = lane_id();
+    const int g4 = 4 * (l / 16);
+    auto act = [](float z) -> float { return __builtin_amdgcn_fmed3f(rintf(z), 0.0f, 255.0f); };
+    bf16x4 h1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        bf16x4 a = {0, 0, 0, 0};
+        if (l < 32) a = load_b4(&W->w1[(nt * 32 + l) * 4]);
+        f32x4 acc = *reinterpret_cast<const f32x4 *>(&W->b1[16 * nt + g4]);
+        acc = mfma16(a, xb, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h1[nt][j] = (short)(__float_as_uint(act(acc[j])) >> 16);
+    }
+    float part = 0.0f;
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 acc = *reinterpret_cast<const f32x4 *>(&W->b2[16 * nt + g4]);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = mfma16(load_b4(&W->w2[((ks * 4 + nt) * 64 + l) * 4]), h1[ks], acc);
+        const f32x4 w3 = *reinterpret_cast<const f32x4 *>(&W->w3[16 * nt + g4]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part = __builtin_fmaf(act(acc[j]), w3[j], part);
+    }
+    // rows 0+1 and 2+3, then the two halves
+    const uint32_t pu = __float_as_uint(part);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(pu, pu, false, false);
+    part = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
+    const uint32_t qu = __float_as_uint(part);
+    const auto s32 = __builtin_amdgcn_permlane32_swap(qu, qu, false, false);
+    part = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+    return part * (1.0f / 64.0f) + W->b3;
 }
 
 // ------------------------------------------------------------- training
@@ -202,7 +231,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *P, const float
     for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles_total; t += (int64_t)gridDim.x * 4) {
         f32x4 z1[4], z2[4];
         float lg[4];
-        mlp_tile_forward<false>(&W, &tiles[wave], load_x_tile(X, n, 16 * t), z1, z2, lg);
+        mlp_tile_forward(&W, &tiles[wave], load_x_tile(X, n, 16 * t), z1, z2, lg);
         if (l % 16 == 15)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -267,7 +296,7 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float *P, const floa
         const int64_t base = 16 * t;
         f32x4 z1[4], z2[4];
         float lg[4];
-        mlp_tile_forward<false>(&W, T, load_x_tile(X, n, base), z1, z2, lg);
+        mlp_tile_forward(&W, T, load_x_tile(X, n, base), z1, z2, lg);
         float dl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

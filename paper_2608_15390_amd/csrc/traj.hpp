@@ -916,15 +916,8 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
             const float lo = __shfl(x[j], src), hi = __shfl(x[4 + j], src);
             xa[j] = grp == 0 ? to_bf16(lo) : (grp == 1 ? to_bf16(hi) : (short)0);
         }
-        f32x4 z1[4], z2[4];
-        float lg[4];
-        mlp_tile_forward<true>(W, tile, xa, z1, z2, lg);
-        // row i = l % 16 of the tile: lane group i / 4 (its last lane), register i % 4
-        const int row = l & 15, from = 16 * (row >> 2) + 15;
-        const float v0 = __shfl(lg[0], from), v1 = __shfl(lg[1], from);
-        const float v2 = __shfl(lg[2], from), v3 = __shfl(lg[3], from);
-        const int js = row & 3;
-        const float y = js == 0 ? v0 : (js == 1 ? v1 : (js == 2 ? v2 : v3));
+        // every lane: the logit of record l % 16 of this tile
+        const float y = mlp_tile_logit_grid(W, xa);
         if (grp == ti) {
             float L = rintf(y * 16.0f);
             L = L < -1024.0f ? -1024.0f : (L > 1023.0f ? 1023.0f : L);

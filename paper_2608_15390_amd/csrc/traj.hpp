@@ -911,10 +911,21 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
     for (int ti = 0; ti < ntiles; ++ti) {
         const int src = 16 * ti + (l & 15);
         bf16x4 xa;
+        if (ti == 0) {
+            // candidates 0..15 sit in lanes 0..15: row 0 keeps its own
+            // features 0..3, and a row swap gives row 1 their features 4..7
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float lo = __shfl(x[j], src), hi = __shfl(x[4 + j], src);
-            xa[j] = grp == 0 ? to_bf16(lo) : (grp == 1 ? to_bf16(hi) : (short)0);
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t xu = __float_as_uint(x[4 + j]);
+                const float hi = __uint_as_float(__builtin_amdgcn_permlane16_swap(xu, xu, false, false)[0]);
+                xa[j] = grp == 0 ? to_bf16(x[j]) : (grp == 1 ? to_bf16(hi) : (short)0);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float lo = __shfl(x[j], src), hi = __shfl(x[4 + j], src);
+                xa[j] = grp == 0 ? to_bf16(lo) : (grp == 1 ? to_bf16(hi) : (short)0);
+            }
         }
         // every lane: the logit of record l % 16 of this tile
         const float y = mlp_tile_logit_grid(W, xa);

@@ -315,8 +315,13 @@ int perm_est_mlp_loss_grad(perm_est_mlp_t *t, const float *x, const float *y, co
 /* Train for `epochs` passes over groups 0..n_groups-1 in windows of
  * `batch_groups` consecutive groups, window order reshuffled each epoch
  * from `seed`; Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
- * after every window.  loss_per_epoch: host double[epochs] (mean window
- * loss), or NULL.  Errors: PE_EINVAL, PE_ENOMEM, PE_EDEVICE. */
+ * after every window.  The groups are first put in a canonical order,
+ * sorted by (matrix, trajectory, step) from ginfo, on a device copy of the
+ * recording (the caller's arrays are not changed), so that the trained
+ * parameters do not depend on the order in which a recording claimed its
+ * slots: the same set of groups, seed and settings give the same
+ * parameters.  loss_per_epoch: host double[epochs] (mean window loss), or
+ * NULL.  Errors: PE_EINVAL, PE_ENOMEM, PE_EDEVICE. */
 int perm_est_mlp_train(perm_est_mlp_t *t, const float *x, const float *y, const int64_t *gstart,
                        const int32_t *ginfo, int64_t n_groups, int32_t epochs, int64_t batch_groups,
                        double lr, uint64_t seed, double *loss_per_epoch, void *stream);

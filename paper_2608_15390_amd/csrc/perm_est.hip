@@ -1000,6 +1000,23 @@ int load_groups(const int64_t *gstart, const int32_t *ginfo, int64_t g0, int64_t
     return PE_OK;
 }
 
+// out[i] = in[src[i]] for records (8 features and one target each)
+__global__ void k_gather_records(const float *x, const float *y, const int64_t *src, int64_t n, float *xo,
+                                 float *yo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = src[i];
+#pragma unroll
+    for (int f = 0; f < kIn; ++f) xo[i * kIn + f] = x[r * kIn + f];
+    yo[i] = y[r];
+}
+
+// device buffers freed on every return path
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
 int mlp_adam(perm_est_mlp *t, double lr, hipStream_t s) {
     t->step += 1;
     const double b1 = 0.9, b2 = 0.999;
@@ -1008,6 +1025,40 @@ int mlp_adam(perm_est_mlp *t, double lr, hipStream_t s) {
     k_adam<<<blocks_for(kNParam), 256, 0, s>>>(t->P, t->grad, t->m, t->v, kNParam, (float)lr, (float)b1, (float)b2,
                                                1e-8f, c1, c2);
     PE_HIP(hipGetLastError());
+    return PE_OK;
+}
+
+// the training loop over windows of a recording in canonical group order
+int mlp_train_windows(perm_est_mlp *t, const float *x, const float *y, const int64_t *gstart,
+                      const int32_t *ginfo, const std::vector<int64_t> &gs, const std::vector<int32_t> &gi,
+                      int64_t n_groups, int32_t epochs, int64_t batch_groups, double lr, uint64_t seed,
+                      double *loss_per_epoch, hipStream_t s) {
+    int rc;
+    const int64_t nwin = (n_groups + batch_groups - 1) / batch_groups;
+    std::vector<int64_t> order(nwin);
+    for (int64_t w = 0; w < nwin; ++w) order[w] = w;
+    uint64_t rs = seed;
+    auto next = [&]() {  // SplitMix64 stream for the window shuffle
+        uint64_t z = (rs += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (int32_t ep = 0; ep < epochs; ++ep) {
+        for (int64_t w = nwin - 1; w > 0; --w) std::swap(order[w], order[(int64_t)(next() % (uint64_t)(w + 1))]);
+        k_fill_f32n<<<1, 64, 0, s>>>(2, reinterpret_cast<float *>(t->loss), 0.0f);
+        for (int64_t w : order) {
+            const int64_t g0 = w * batch_groups, g1 = std::min<int64_t>(n_groups, g0 + batch_groups);
+            const int64_t r0 = gs[g0], n = gs[g1 - 1] + gi[4 * (g1 - 1)] - r0;
+            if ((rc = mlp_window(t, x, y, gstart, ginfo, g0, g1, r0, n, t->grad, s))) return rc;
+            if ((rc = mlp_adam(t, lr, s))) return rc;
+        }
+        double ls = 0.0;
+        PE_HIP(hipMemcpyAsync(&ls, t->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+        PE_HIP(hipStreamSynchronize(s));
+        if (loss_per_epoch) loss_per_epoch[ep] = ls / (double)nwin;
+    }
+    PE_HIP(hipStreamSynchronize(s));
     return PE_OK;
 }
 
@@ -1309,33 +1360,59 @@ int perm_est_mlp_train(perm_est_mlp_t *t, const float *x, const float *y, const 
     std::vector<int32_t> gi;
     int rc;
     if ((rc = load_groups(gstart, ginfo, 0, n_groups, s, gs, gi))) return rc;
-    const int64_t nwin = (n_groups + batch_groups - 1) / batch_groups;
-    std::vector<int64_t> order(nwin);
-    for (int64_t w = 0; w < nwin; ++w) order[w] = w;
-    uint64_t rs = seed;
-    auto next = [&]() {  // SplitMix64 stream for the window shuffle
-        uint64_t z = (rs += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    };
-    for (int32_t ep = 0; ep < epochs; ++ep) {
-        for (int64_t w = nwin - 1; w > 0; --w) std::swap(order[w], order[(int64_t)(next() % (uint64_t)(w + 1))]);
-        k_fill_f32n<<<1, 64, 0, s>>>(2, reinterpret_cast<float *>(t->loss), 0.0f);
-        for (int64_t w : order) {
-            const int64_t g0 = w * batch_groups, g1 = std::min<int64_t>(n_groups, g0 + batch_groups);
-            const int64_t r0 = gs[g0], n = gs[g1 - 1] + gi[4 * (g1 - 1)] - r0;
-            if ((rc = mlp_window(t, x, y, gstart, ginfo, g0, g1, r0, n, t->grad, s))) return rc;
-            if ((rc = mlp_adam(t, lr, s))) return rc;
+    // canonical order of the groups: (matrix, trajectory, step)
+    {
+        std::vector<int64_t> perm((size_t)n_groups);
+        for (int64_t g = 0; g < n_groups; ++g) perm[(size_t)g] = g;
+        std::sort(perm.begin(), perm.end(), [&](int64_t p, int64_t q) {
+            for (int f = 1; f < 4; ++f)
+                if (gi[4 * p + f] != gi[4 * q + f]) return gi[4 * p + f] < gi[4 * q + f];
+            return p < q;
+        });
+        const int64_t n_rec = gs.back() + gi[4 * (n_groups - 1)] - gs.front();
+        std::vector<int64_t> src;
+        src.reserve((size_t)n_rec);
+        std::vector<int64_t> gs2((size_t)n_groups);
+        std::vector<int32_t> gi2(4 * (size_t)n_groups);
+        int64_t pos = 0;
+        for (int64_t i = 0; i < n_groups; ++i) {
+            const int64_t g = perm[(size_t)i];
+            gs2[(size_t)i] = pos;
+            for (int f = 0; f < 4; ++f) gi2[4 * (size_t)i + f] = gi[4 * g + f];
+            for (int32_t r = 0; r < gi[4 * g]; ++r) src.push_back(gs[g] + r);
+            pos += gi[4 * g];
         }
-        double ls = 0.0;
-        PE_HIP(hipMemcpyAsync(&ls, t->loss, sizeof(double), hipMemcpyDeviceToHost, s));
-        PE_HIP(hipStreamSynchronize(s));
-        if (loss_per_epoch) loss_per_epoch[ep] = ls / (double)nwin;
+        gs.swap(gs2);
+        gi.swap(gi2);
+        DevBuf b_src, b_x, b_y, b_gs, b_gi;
+        int64_t *d_src;
+        float *d_x, *d_y;
+        int64_t *d_gs;
+        int32_t *d_gi;
+        if ((rc = dalloc(&d_src, (size_t)n_rec))) return rc;
+        b_src.p = d_src;
+        if ((rc = dalloc(&d_x, (size_t)n_rec * kIn))) return rc;
+        b_x.p = d_x;
+        if ((rc = dalloc(&d_y, (size_t)n_rec))) return rc;
+        b_y.p = d_y;
+        if ((rc = dalloc(&d_gs, (size_t)n_groups))) return rc;
+        b_gs.p = d_gs;
+        if ((rc = dalloc(&d_gi, 4 * (size_t)n_groups))) return rc;
+        b_gi.p = d_gi;
+        PE_HIP(hipMemcpyAsync(d_src, src.data(), sizeof(int64_t) * (size_t)n_rec, hipMemcpyHostToDevice, s));
+        PE_HIP(hipMemcpyAsync(d_gs, gs.data(), sizeof(int64_t) * (size_t)n_groups, hipMemcpyHostToDevice, s));
+        PE_HIP(hipMemcpyAsync(d_gi, gi.data(), sizeof(int32_t) * 4 * (size_t)n_groups, hipMemcpyHostToDevice, s));
+        k_gather_records<<<blocks_for(n_rec), 256, 0, s>>>(x, y, d_src, n_rec, d_x, d_y);
+        PE_HIP(hipGetLastError());
+        rc = mlp_train_windows(t, d_x, d_y, d_gs, d_gi, gs, gi, n_groups, epochs, batch_groups, lr, seed,
+                               loss_per_epoch, s);
+        // the copies are freed when this block ends; wait for the last use
+        hipError_t e = hipStreamSynchronize(s);
+        if (rc == PE_OK && e != hipSuccess) return fail(PE_EDEVICE, hipGetErrorString(e));
+        return rc;
     }
-    PE_HIP(hipStreamSynchronize(s));
-    return PE_OK;
 }
+
 
 void perm_est_mlp_destroy(perm_est_mlp_t *t) {
     if (!t) return;

@@ -118,6 +118,48 @@ def test_training_lowers_the_loss():
     net.close()
 
 
+def test_training_is_independent_of_the_recording_order():
+    """Groups are put in (matrix, trajectory, step) order before training, so
+    a recording whose groups sit in another order trains to the same
+    parameters bit for bit; two recordings of the same runs (whose slot
+    claims race) do too."""
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import learned as LR
+    X, y, off = _groups(5, groups=700)
+    G_ = len(off) - 1
+    g = np.random.default_rng(6)
+    keys = np.stack([g.integers(0, 3, G_), g.permutation(G_), g.integers(0, 50, G_)], axis=1).astype(np.int32)
+    perm = g.permutation(G_)
+    sizes = np.diff(off)
+    Xp = np.concatenate([X[off[i]:off[i + 1]] for i in perm])
+    yp = np.concatenate([y[off[i]:off[i + 1]] for i in perm])
+    offp = np.concatenate([[0], np.cumsum(sizes[perm])])
+
+    def rec(Xa, ya, offa, ka):
+        gi = np.zeros((len(offa) - 1, 4), dtype=np.int32)
+        gi[:, 0] = np.diff(offa)
+        gi[:, 1:] = ka
+        return {"x": _dev(Xa, torch.float32), "y": _dev(ya, torch.float32),
+                "gstart": _dev(offa[:-1], torch.int64), "ginfo": _dev(gi, torch.int32), "n_groups": len(offa) - 1}
+
+    outs = []
+    for r in (rec(X, y, off, keys), rec(Xp, yp, offp, keys[perm])):
+        net = P.ProposalNet(R.init(9).astype(np.float32))
+        net.train(r, epochs=3, batch_groups=64, lr=2e-3, seed=4)
+        outs.append(net.params().cpu().numpy())
+        net.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+    # two recordings of the same teacher runs
+    mats = G.config_train(2, count=24, n=200)
+    params = []
+    for _ in range(2):
+        r = LR.record_pairs(mats, n_traj=2, seed=3)
+        p, _ = LR.train(r, epochs=2, seed=2)
+        params.append(p.cpu().numpy())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(params[0], params[1])
+
+
 def _osched(g, model=None, mix_alpha=0.05):
     return O.Schedule(vertex_rule=g.vertex_rule, sk_policy=g.sk_policy, dm_policy=g.dm_policy,
                       initial_dm=g.initial_dm, K0=g.K0, K=g.K, theta_th=g.theta_th, theta_tr=g.theta_tr,

@@ -274,9 +274,11 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
             // ---- minimum-degree selection down the row's min-tree, then the leaf group
             int32_t v = -1, gsel = -1;
             uint4 lq0 = make_uint4(0, 0, 0, 0), lq1 = lq0;  // this lane's 16 leaves of v's group
+            uint32_t m_sel = 0;  // the minimum degree at selection
             {
                 const int top = a.tree.levels - 1;
                 const uint32_t m = T.global_min();
+                m_sel = m;
                 int32_t g = 0;
                 for (int kk = top; kk >= 0 && g >= 0; --kk) {
                     // first node of the block [64 g, 64 g + 64) of level kk holding m
@@ -468,19 +470,26 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 }
                 const int32_t gu = u >> 8;
                 const uint32_t l1u_before = T.level(0)[gu];
+                // u's group needs a new minimum when u is it: read its leaves
+                // before this step's stores (stale values are only higher;
+                // the new degrees and u are patched in below)
+                const bool refresh_u = gu != gsel && d_u <= l1u_before;
+                uint4 uq0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), uq1 = uq0;
+                if (refresh_u) T.load_leaves(gu, uq0, uq1);
                 wave_fence();
                 // retire v and u, lower their other neighbours
                 if (rl == 0) {
                     T.deg[v] = kRetired;
                     T.deg[u] = kRetired;
                 }
-                uint32_t dec_min_g = 0xFFFFFFFFu;
+                uint32_t dec_min_g = 0xFFFFFFFFu, dec_min_u = 0xFFFFFFFFu;
                 if (fast_v) {
                     if (cand && cy != u) {
                         const uint32_t nd = cd - 1u;
                         T.deg[cy] = (uint16_t)nd;
                         T.tree_lower(cy, nd);
                         if ((cy >> 8) == gsel) dec_min_g = nd;
+                        if ((cy >> 8) == gu) dec_min_u = nd;
                     }
                 } else {
                     for (int32_t idx = rl; idx < kc; idx += kRowLanes) {
@@ -490,6 +499,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                         T.deg[y] = (uint16_t)nd;
                         T.tree_lower(y, nd);
                         if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+                        if ((y >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
                     }
                 }
                 if (fast_u) {
@@ -498,6 +508,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                         T.deg[by] = (uint16_t)nd;
                         T.tree_lower(by, nd);
                         if ((by >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+                        if ((by >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
                     }
                 } else {
                     for (int32_t idx = rl; idx < kb; idx += kRowLanes) {
@@ -506,6 +517,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                         T.deg[y] = (uint16_t)nd;
                         T.tree_lower(y, nd);
                         if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
+                        if ((y >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
                     }
                 }
                 if (rl == 0) {
@@ -519,19 +531,20 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                     mm = row_min_u32(mm < dec_min_g ? mm : dec_min_g);
                     if (rl == 0) T.level(0)[gsel] = mm;
                     wave_fence();
-                    T.refresh_upper(gsel);
+                    // the upper levels hold every lowered value already
+                    if (mm > m_sel) T.refresh_upper(gsel);
                 }
-                if (gu != gsel && d_u <= l1u_before) {
-                    uint4 p0, p1;
-                    T.load_leaves(gu, p0, p1);
-                    const uint32_t mu = row_min_u32(min16(p0, p1));
+                if (refresh_u) {
+                    uint32_t mu = min16_skip(uq0, uq1, 256 * gu + 16 * rl, v, u);
+                    mu = row_min_u32(mu < dec_min_u ? mu : dec_min_u);
                     if (rl == 0) T.level(0)[gu] = mu;
                     wave_fence();
-                    T.refresh_upper(gu);
+                    if (mu > d_u) T.refresh_upper(gu);
                 }
                 steps = t + 1;
                 t += 1;
-                if (t < n && T.global_min() == 0) alive = false;  // child dead end
+                // a dead child is found by the next selection (a degree-0
+                // vertex without candidates), at the same step count
             }
             finished = !alive || t >= n;
         }

@@ -51,3 +51,14 @@ def test_bootstrap_interval_brackets_the_mean():
     assert lo <= np.mean(v) <= hi
     assert min(v) <= lo and hi <= max(v)
     assert bench.bootstrap_ci([2.0] * 5) == [2.0, 2.0]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""

@@ -253,14 +253,20 @@ struct Traj {
         }
         if (!hit) return false;
         leaves = recast<const uint2>(deg + 256 * g)[l];
-        int32_t lb[4], le[4];
+        // list bounds of this lane's four vertices from five consecutive
+        // pointers (a list ends where the next begins, except at the last row)
+        int32_t pp[5], lb[4], le[4];
+        const int32_t x0 = 256 * g + 4 * l;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int32_t x = x0 + i;
+            const int32_t xc = x - n < n ? x - n : n;  // past the columns: their end
+            pp[i] = *(x < n ? M.row_ptr + x : M.col_ptr + xc);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int32_t x = 256 * g + 4 * l + i;
-            lb[i] = 0;
-            le[i] = 0;
-            if (x < n) { lb[i] = M.row_ptr[x]; le[i] = M.row_ptr[x + 1]; }
-            else if (x < 2 * n) { lb[i] = M.col_ptr[x - n]; le[i] = M.col_ptr[x - n + 1]; }
+            lb[i] = pp[i];
+            le[i] = x0 + i == n - 1 ? M.row_ptr[n] : pp[i + 1];
         }
         const uint32_t d0 = leaves.x & 0xFFFFu, d1 = leaves.x >> 16, d2 = leaves.y & 0xFFFFu,
                        d3 = leaves.y >> 16;
@@ -800,6 +806,12 @@ __device__ __forceinline__ void learned_features(float *x, uint32_t deg_rho, uin
     x[7] = (float)(c2_u < 255 ? c2_u : 255) / 64.0f;
 }
 
+// per-wave LDS scratch of the learned proposal (the owner search of the
+// flattened candidate lists; the network itself runs in registers)
+struct WaveScratch {
+    int32_t i[kWave];
+};
+
 // The candidates' flattened lists as read by candidate_stats when they fit
 // one pass of the wave: the step reuses them for N_t(u) once u is drawn.
 struct NbrCache {
@@ -897,7 +909,7 @@ __device__ void candidate_stats(const TT &T, bool cand, int32_t u, int32_t ub, i
 // feature tile assembled and the logits returned by cross-lane moves (only
 // the layer-1 activations pass through LDS).  Lanes without a candidate
 // return 0.
-__device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uint32_t deg_rho,
+__device__ int32_t learned_logits(const MlpLds *W, bool cand, uint32_t deg_rho,
                                   uint32_t deg_gam, float r0_rho, float c0_gam, int32_t k4,
                                   bool v_row, uint64_t s_u, int32_t c2_u, int32_t chunk_len) {
     const int l = lane_id();
@@ -940,7 +952,7 @@ __device__ int32_t learned_logits(const MlpLds *W, TileLds *tile, bool cand, uin
 
 template <int SK, bool DM, bool WT, int AS>
 __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Traj<OwnRC<SK>::value, DM, WT, AS> &T,
-                                               int64_t q, Work &work, const LearnedLds *lrn, TileLds *mlps) {
+                                               int64_t q, Work &work, const LearnedLds *lrn, WaveScratch *scr) {
     const MlpLds *mlpw = &lrn->net;
     const uint32_t *etab = lrn->etab;
     constexpr bool OWN = OwnRC<SK>::value;
@@ -1041,8 +1053,8 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     const float c0g = T.c0 ? T.c0[cand ? gam_c - n : 0] : 1.0f;
                     uint64_t su;
                     int32_t c2;
-                    candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc, reinterpret_cast<int32_t *>(mlps->h));
-                    L = learned_logits(mlpw, mlps, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
+                    candidate_stats(T, cand, cy, cub, cue, v, su, c2, nc, scr->i);
+                    L = learned_logits(mlpw, cand, v_row ? deg_v : cd, v_row ? cd : deg_v, r0r, c0g,
                                        k4, v_row, su, c2, ve - vb);
                     work.mlp_tiles += (uint64_t)((ve - vb + 15) / 16);
                 }
@@ -1185,8 +1197,8 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                     int32_t yub = 0, yue = 0;
                     if (c0) T.list(y, yub, yue);
                     NbrCache lnc;
-                    candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc, reinterpret_cast<int32_t *>(mlps->h));
-                    const int32_t L = learned_logits(mlpw, mlps, c0, v_row ? (uint32_t)kc : dy,
+                    candidate_stats(T, c0, y, yub, yue, v, su, c2, lnc, scr->i);
+                    const int32_t L = learned_logits(mlpw, c0, v_row ? (uint32_t)kc : dy,
                                                      v_row ? dy : (uint32_t)kc, r0r, c0g, k4, v_row, su, c2,
                                                      min(kWave, ve - base));
                     work.mlp_tiles += (uint64_t)((min(kWave, ve - base) + 15) / 16);
@@ -1519,7 +1531,7 @@ struct BatchArgs {
     const int64_t *etab;      // learned proposal's softmax table (staged per block)
 };
 
-constexpr int kMlpWaveBytes = (int)sizeof(TileLds);
+constexpr int kMlpWaveBytes = (int)sizeof(WaveScratch);
 constexpr int kMlpBlockBytes = ((int)sizeof(LearnedLds) + 15) / 16 * 16;
 
 // The argument blocks live in device memory (uniform fields become scalar
@@ -1542,7 +1554,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     const size_t per_wave = (size_t)B.lds_tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)B.lds_state_bytes;
     char *mine = waves + (size_t)wave * per_wave;
     uint32_t *tree = reinterpret_cast<uint32_t *>(mine);
-    TileLds *mlps = reinterpret_cast<TileLds *>(mine + B.lds_tree_bytes);
+    WaveScratch *scr = reinterpret_cast<WaveScratch *>(mine + B.lds_tree_bytes);
     // per-matrix tier: the wave's LDS slot (sized for the largest LDS-tier
     // matrix of the launch) or its HBM slot
     char *lds_state = mine + B.lds_tree_bytes + B.lds_mlp_bytes;
@@ -1564,10 +1576,10 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
         const int64_t k = (int64_t)q - gptr(B.item_off)[lo];
         if (a.lds_tier) {
             const Traj<OwnRC<SK>::value, DM, WT, kAsLds> T(a, lds_state, tree);
-            run_trajectory<SK, DM, WT, kAsLds>(a, T, k, work, lrn, mlps);
+            run_trajectory<SK, DM, WT, kAsLds>(a, T, k, work, lrn, scr);
         } else {
             const Traj<OwnRC<SK>::value, DM, WT, kAsGlobal> T(a, hbm_state, tree);
-            run_trajectory<SK, DM, WT, kAsGlobal>(a, T, k, work, lrn, mlps);
+            run_trajectory<SK, DM, WT, kAsGlobal>(a, T, k, work, lrn, scr);
         }
     }
     if (lane_id() == 0 && B.work_totals) {

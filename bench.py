@@ -223,38 +223,47 @@ def ladder(params, plain_sched, learned_sched, seeds):
     return rows
 
 
+BAND_SIZES = ((1000, "1e3", 100_000), (10_000, "1e4", 20_000), (100_000, "1e5", 10_000))
+
+
 def band_study(params, plain_sched, learned_sched, seed, cnt):
-    """Both methods on the n = 1e5 band matrix of mean degree 8 whose
-    permanent is known exactly (stored reference, dynamic program over the
-    band): the true relative error of each estimate."""
+    """Both methods on band matrices of mean degree 8 whose permanent is known
+    exactly (stored references, dynamic program over the band), at n = 1e3,
+    1e4 (100000 and 20000 trajectories) and 1e5 (`cnt`): the true error of
+    each estimate, so "equal relative error" can be read off directly."""
     import paper_2608_15390_amd as P
     from paper_2608_15390_amd import inputs as G
     from paper_2608_15390_amd import learned as LR
 
-    with open(os.path.join(ROOT, "tests", "golden", "band_n1e5_hw4.json")) as f:
-        ref = json.load(f)
-    M, _ = G.config_band(1)
-    h = hashlib.sha256()
-    for a in (M.row_ptr, M.col_idx, M.col_ptr, M.row_idx):
-        h.update(a.astype("<i4").tobytes())
-    if h.hexdigest() != ref["index_sha256"]:
-        return {"error": "the generator no longer builds the stored band matrix"}
-    lp = ref["log_permanent"]
-    est = P.PermEst(M)
-    est.set_model(params, LR.MIX_ALPHA)
-    out = {"n": M.n, "nnz": M.nnz, "n_traj": cnt, "log_permanent": lp}
-    for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
-        est.run(0, 64, seed, sch, want_logw=False, want_alive=False)
-        res, secs = timed_run(est, 0, cnt, seed, sch)
-        rec = summary(res["result"], secs)
-        le = rec["log_estimate"]
-        rec["log_error"] = le - lp
-        rec["rel_error"] = math.expm1(le - lp) if math.isfinite(le) else -1.0
-        out[name] = rec
-        print(f"[bench]   band n=1e5 {name}: rel error {rec['rel_error']:.3g}, {secs:.1f} s",
-              file=sys.stderr, flush=True)
-    est.close()
-    return out
+    rows = []
+    for n, tag, count in BAND_SIZES:
+        count = cnt if n == 100_000 else count
+        with open(os.path.join(ROOT, "tests", "golden", f"band_n{tag}_hw4.json")) as f:
+            ref = json.load(f)
+        M, _ = G.config_band(1, n=n)
+        h = hashlib.sha256()
+        for a in (M.row_ptr, M.col_idx, M.col_ptr, M.row_idx):
+            h.update(a.astype("<i4").tobytes())
+        if h.hexdigest() != ref["index_sha256"]:
+            rows.append({"n": n, "error": "the generator no longer builds the stored band matrix"})
+            continue
+        lp = ref["log_permanent"]
+        est = P.PermEst(M)
+        est.set_model(params, LR.MIX_ALPHA)
+        out = {"n": M.n, "nnz": M.nnz, "n_traj": count, "log_permanent": lp}
+        for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
+            est.run(0, 64, seed, sch, want_logw=False, want_alive=False)
+            res, secs = timed_run(est, 0, count, seed, sch)
+            rec = summary(res["result"], secs)
+            le = rec["log_estimate"]
+            rec["log_error"] = le - lp
+            rec["rel_error"] = math.expm1(le - lp) if math.isfinite(le) else -1.0
+            out[name] = rec
+            print(f"[bench]   band n={n} {name}: rel error {rec['rel_error']:.3g}, {secs:.1f} s",
+                  file=sys.stderr, flush=True)
+        est.close()
+        rows.append(out)
+    return rows
 
 
 def batch_main(args) -> int:
@@ -475,7 +484,7 @@ def main() -> int:
         learned_s, plain_s = (mine, theirs) if args.method == "learned" else (theirs, mine)
         print("[bench] ladder n=1e3, 1e4", file=sys.stderr, flush=True)
         lad = ladder(params, plain_sched, learned_sched, [args.seed + i for i in range(args.ladder_seeds)])
-        print("[bench] band matrix n=1e5 (exact permanent known)", file=sys.stderr, flush=True)
+        print("[bench] band matrices n=1e3, 1e4, 1e5 (exact permanent known)", file=sys.stderr, flush=True)
         band = band_study(params, plain_sched, learned_sched, args.seed, args.band_traj)
         line["compare"] = {
             "plain_schedule": args.plain_schedule,

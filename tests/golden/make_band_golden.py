@@ -1,9 +1,10 @@
-"""Writes band_n1e5_hw4.json: the exact ln per(A) of the n = 1e5 band matrix
-of mean degree 8 (half-width 4, inner band full, outermost diagonals kept
-with probability 1/2, rows and columns permuted; generator seed 1), computed by
-the oracle's dynamic program over the band.  The index arrays' digest is
-stored with it so that a reader can tell that the generator still builds the
-same matrix.
+"""Writes band_n1e3_hw4.json, band_n1e4_hw4.json and band_n1e5_hw4.json: the
+exact ln per(A) of the band matrices of mean degree 8 at n = 1e3, 1e4, 1e5
+(half-width 4, inner band full, outermost diagonals kept with probability
+1/2, rows and columns permuted; generator seed 1), computed by the oracle's
+dynamic program over the band.  The index arrays' digest is stored with
+each, so that a reader can tell that the generator still builds the same
+matrix.
 
 Run from the repository root:  python tests/golden/make_band_golden.py
 """
@@ -28,21 +29,26 @@ def digest(M) -> str:
     return h.hexdigest()
 
 
+SIZES = {"1e3": 1000, "1e4": 10_000, "1e5": 100_000}
+
+
 def main() -> None:
-    M, band = G.config_band(1)
-    out = {
-        "matrix": "inputs.config_band(seed=1): n = 1e5, band half-width 4, outer diagonals kept with probability 1/2, permuted",
-        "n": M.n,
-        "nnz": M.nnz,
-        "index_sha256": digest(M),
-        "log_permanent": B.band_log_permanent(band, 4),
-        "method": "oracle/band.py band_log_permanent (float64, rescaled per row)",
-    }
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "band_n1e5_hw4.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-        f.write("\n")
-    print(json.dumps(out))
+    for tag, n in SIZES.items():
+        M, band = G.config_band(1, n=n)
+        out = {
+            "matrix": f"inputs.config_band(seed=1, n={n}): band half-width 4, outer diagonals kept with "
+                      "probability 1/2, permuted",
+            "n": M.n,
+            "nnz": M.nnz,
+            "index_sha256": digest(M),
+            "log_permanent": B.band_log_permanent(band, 4),
+            "method": "oracle/band.py band_log_permanent (float64, rescaled per row)",
+        }
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"band_n{tag}_hw4.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+            f.write("\n")
+        print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -20,9 +20,6 @@ from oracle import band as B
 from oracle import oracle as O
 from paper_2608_15390_amd import inputs as G
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "band_n1e5_hw4.json")
-
-
 def _brute(D):
     n = D.shape[0]
     return sum(math.prod(D[i, p[i]] for i in range(n)) for p in itertools.permutations(range(n)))
@@ -99,12 +96,13 @@ def test_estimator_mean_within_ci_of_band_permanent(n, name):
     assert abs(math.exp(st["log_estimate"] - lp) - 1.0) <= 4.5 * st["rse"], (st, lp)
 
 
-def test_stored_large_band_permanent():
-    """The stored ln per(A) of the n = 1e5 band workload is what the dynamic
-    program gives for the matrix the generator builds today."""
-    with open(GOLDEN) as f:
+@pytest.mark.parametrize("tag,n", [("1e3", 1000), ("1e4", 10_000), ("1e5", 100_000)])
+def test_stored_band_permanents(tag, n):
+    """The stored ln per(A) of the band workloads is what the dynamic
+    program gives for the matrices the generator builds today."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", f"band_n{tag}_hw4.json")) as f:
         g = json.load(f)
-    M, band = G.config_band(1)
+    M, band = G.config_band(1, n=n)
     h = hashlib.sha256()
     for a in (M.row_ptr, M.col_idx, M.col_ptr, M.row_idx):
         h.update(a.astype("<i4").tobytes())

@@ -44,13 +44,26 @@ MIX_ALPHA = 0.01  # uniform share mixed into the learned proposal
 
 def record_pairs(mats: List[SparseMatrix], n_traj: int = 4, seed: int = 1, stride: int = 1,
                  device: int = 0) -> Dict:
-    """Training pairs from the teacher schedule over a batch of matrices."""
+    """Training pairs from the teacher schedule over a batch of matrices.
+
+    A step records at most 64 pairs and the buffer is sized for 12 per step
+    on average; a claim that does not fit is dropped, which can only happen
+    once fewer than 64 slots are left.  If the recording got that close to
+    full it is repeated with four times the room (so that the set of groups,
+    and with the trainer's canonical order the trained network, does not
+    depend on which claims won); `complete` says whether every group fit."""
     steps = sum(int(M.n) for M in mats) * n_traj
-    rec_cap = int(min((1 << 31) - 1, 12 * steps // stride + 64))
     group_cap = int(min((1 << 31) - 1, steps // stride + 64))
     bt = PermEstBatch(mats, device=device)
     t = time.perf_counter()
-    rec = bt.record(n_traj, seed, teacher_schedule(), rec_cap=rec_cap, group_cap=group_cap, stride=stride)
+    per_step = 12
+    while True:
+        rec_cap = int(min((1 << 31) - 1, per_step * steps // stride + 64))
+        rec = bt.record(n_traj, seed, teacher_schedule(), rec_cap=rec_cap, group_cap=group_cap, stride=stride)
+        rec["complete"] = rec["n_records"] + 64 <= rec_cap
+        if rec["complete"] or per_step >= 64 or rec_cap == (1 << 31) - 1:
+            break
+        per_step = min(64, per_step * 4)
     rec["seconds"] = time.perf_counter() - t
     bt.close()
     return rec
@@ -77,4 +90,5 @@ def train_proposal(mats: List[SparseMatrix], *, n_traj: int = 4, stride: int = 1
     rec = record_pairs(mats, n_traj=n_traj, seed=seed, stride=stride, device=device)
     params, info = train(rec, epochs=epochs, batch_groups=batch_groups, lr=lr, seed=seed, device=device)
     info["record_seconds"] = rec["seconds"]
+    info["recording_complete"] = rec["complete"]
     return params, info

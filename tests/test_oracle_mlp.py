@@ -211,3 +211,54 @@ def test_softmax_table_is_rounding_stable_and_matches_the_oracle():
         S = (1 << 24) + e
         assert w[0] == max(1, round((1 << 24) * ((1 << 24) / S)))
         assert w[1] == max(1, round((1 << 24) * (e / S)))
+
+
+def test_feature_definitions_have_exact_integer_forms():
+    """The FP64 definitions of the logarithmic and phase features equal
+    integer forms read off the inputs' bits (the forms the matrix-core
+    kernel uses): for a positive normal binary32 s, 64 plog2(s)/4 is
+    (bits >> 19) - 2032 plus the low 19 bits over 2^19, rounded half to even;
+    for an integer S >= 1 with 2^p <= S < 2^(p+1), 16 plog2(S / 2^20) is
+    16 p + 16 S / 2^p - 16 - 320; rint(64 t / n) is the exact rational's
+    rounding. Checked against the oracle's features on ties, powers of two
+    and random values."""
+    import struct
+
+    def clamp(k):
+        return min(255, max(-256, k))
+
+    def from_bits(s):
+        b = struct.unpack("<I", struct.pack("<f", s))[0]
+        q, r = b >> 19, b & 0x7FFFF
+        return clamp(q + (1 if (r > 0x40000 or (r == 0x40000 and q & 1)) else 0) - 2032) / 64.0
+
+    def from_int(S):
+        if S == 0:
+            return clamp(-32) / 64.0
+        p = S.bit_length() - 1
+        t16 = S << 4
+        q = t16 >> p
+        up = 0
+        if p > 0:
+            r, half = t16 & ((1 << p) - 1), 1 << (p - 1)
+            up = 1 if (r > half or (r == half and q & 1)) else 0
+        return clamp(16 * p + q + up - 16 - 320) / 64.0
+
+    g = np.random.default_rng(3)
+    floats = [np.float32(v) for v in g.lognormal(0.0, 3.0, 4000)]
+    floats += [np.float32(2.0 ** k * (1 + j / 16 + 1 / 32)) for k in range(-30, 30, 3) for j in range(16)]
+    floats += [np.float32(2.0 ** k) for k in range(-126, 128, 7)]
+    for s in floats:
+        x = O.learned_features(3, 4, float(s), float(s), 0, 10, 1, 0, 0)
+        assert x[2] == from_bits(s) and x[3] == from_bits(s), s
+    ints = list(range(0, 600)) + [int(v) for v in g.integers(0, 2 ** 40, 3000)]
+    ints += [(2 ** p) * (32 + 2 * j + 1) // 32 for p in range(5, 40) for j in range(16)]
+    for S in ints:
+        x = O.learned_features(3, 4, 1.0, 1.0, 0, 10, 1, S, 0)
+        assert x[6] == from_int(S), S
+    for n in (1, 2, 3, 7, 64, 100, 1000, 12800, 100000):
+        for t in sorted({0, 1, n // 2, n - 1} | set(int(v) for v in g.integers(0, n, 50))):
+            x = O.learned_features(3, 4, 1.0, 1.0, t, n, 1, 0, 0)
+            q, r = divmod(64 * t, n)
+            k = q + (1 if (2 * r > n or (2 * r == n and q & 1)) else 0)
+            assert x[4] == clamp(k) / 64.0, (t, n)

@@ -48,6 +48,7 @@ extern "C" {
 #define PE_EDEVICE (-3)  /* a HIP call failed (message has the HIP error)  */
 #define PE_ENOTSUP (-4)  /* valid request this build does not implement,
                             e.g. a degree above 65534                        */
+#define PE_EIO (-5)      /* a file could not be opened, read or written     */
 
 /* vertex selection rule R_V (Alg. 2 input; Sec. 3.2) */
 #define PE_VR_MD 0        /* two-sided minimum degree over rows and columns,
@@ -99,7 +100,16 @@ typedef struct {
     int32_t K;            /* inner SK cap (>= 0)                            */
     double theta_th;      /* Thrs threshold                                 */
     double theta_tr;      /* Trck threshold                                 */
-    int32_t reserved[4];  /* must be 0                                      */
+    int32_t local_gate;   /* PE_SK_LEARNED only: 1 = gated local-repair
+                             fallback.  The trajectory keeps its own r, c
+                             (from the outer scaling); after a step whose
+                             sampled probability z = w_u / sum w is below
+                             theta_th, or after an inner DM call, it repairs
+                             them by Eq. (local) (Sec. 3.3, Local policy),
+                             and the next step draws from the scaled
+                             proposal of Eq. (q) with z = r_rho c_gam
+                             instead of the network.  0 = network only    */
+    int32_t reserved[3];  /* must be 0                                      */
 } perm_est_schedule;
 
 typedef struct {
@@ -124,6 +134,11 @@ typedef struct {
     int64_t n_local_values;    /* scaling values recomputed by local repair */
     int64_t n_mlp_tiles;       /* 16-candidate tiles through the learned
                                   proposal's network                        */
+    int64_t n_entries_scanned_v; /* the part of n_entries_scanned read at the
+                                    selected vertex v                      */
+    double kernel_seconds;     /* device time of the trajectory kernel alone
+                                  (HIP events on the run's stream); equal to
+                                  `seconds` for a replayed graph            */
 } perm_est_result;
 
 /* Create a handle for one n x n matrix A given in both CSR and CSC form
@@ -150,7 +165,8 @@ int perm_est_create(int32_t n, int64_t nnz,
  * initial DM) -- and "plain" (Alg. 2 with MD, no scaling, no filtering),
  * "rasmussen" (Alg. 1), "local_nodm" (local_threshold without inner DM),
  * "learned" and "learned_threshold" (PE_SK_LEARNED with no inner DM / with
- * Thrs, otherwise as the five variants; the network is set separately).
+ * Thrs, otherwise as the five variants; the network is set separately),
+ * "learned_gated" and "learned_threshold_gated" (the same with local_gate).
  * Errors: PE_EINVAL for an unknown name. */
 int perm_est_schedule_preset(const char *name, perm_est_schedule *out);
 
@@ -253,6 +269,23 @@ int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed,
  * Errors: PE_EINVAL (NULL params, alpha outside [0, 1], a non-finite
  * parameter), PE_ENOMEM, PE_EDEVICE. */
 int perm_est_set_model(perm_est_t *h, const float *params, double mix_alpha, void *stream);
+
+/* Save a network (host float[PE_MLP_NPARAM], e.g. from
+ * perm_est_mlp_get_params) and its uniform share alpha to the file `path`:
+ * the bytes "PEMLP001", the parameter count (uint32), a zero uint32, alpha
+ * (double), the parameters (float), then a 64-bit FNV-1a checksum of all
+ * preceding bytes, little-endian.  Host-only; touches no device.
+ * Errors: PE_EINVAL (NULL, alpha outside [0, 1], a non-finite parameter),
+ * PE_EIO (the file cannot be written). */
+int perm_est_model_save(const char *path, const float *params, double mix_alpha);
+
+/* Read a file written by perm_est_model_save into host params
+ * float[PE_MLP_NPARAM] and *mix_alpha (both left unchanged on error); the
+ * values can then go to perm_est_set_model (after a copy to the device) or
+ * perm_est_mlp_create.  Host-only.
+ * Errors: PE_EINVAL (NULL, wrong size, magic or parameter count, checksum
+ * mismatch, non-finite value, bad alpha), PE_EIO (cannot be opened). */
+int perm_est_model_load(const char *path, float *params, double *mix_alpha);
 
 /* Training-pair buffers (all DEVICE memory, caller-owned).  A group is one
  * recorded step: the candidates of the selected vertex in adjacency order. */

@@ -57,7 +57,7 @@ class _Sched(C.Structure):
         ("theta_th", C.c_double),
         ("theta_tr", C.c_double),
         ("precision", C.c_int32),
-        ("pad", C.c_int32),
+        ("local_gate", C.c_int32),
         ("model", C.c_void_p),
         ("mix_alpha", C.c_double),
     ]
@@ -126,6 +126,7 @@ class Schedule:
     precision: int = CONTRACT
     model: Optional[np.ndarray] = None   # quantised MLP parameters (float64, MLP_NPARAM)
     mix_alpha: float = 0.05
+    local_gate: int = 0                  # learned only: gated local-repair fallback
 
     def c(self) -> _Sched:
         if self.sk_policy == SK_LEARNED:
@@ -136,7 +137,8 @@ class Schedule:
         else:
             mp = None
         return _Sched(self.vertex_rule, self.sk_policy, self.dm_policy, self.initial_dm, self.K0,
-                      self.K, self.theta_th, self.theta_tr, self.precision, 0, mp, self.mix_alpha)
+                      self.K, self.theta_th, self.theta_tr, self.precision, self.local_gate, mp,
+                      self.mix_alpha)
 
     def replace(self, **kw) -> "Schedule":
         d = {k: v for k, v in self.__dict__.items() if not k.startswith("_")}
@@ -161,6 +163,9 @@ def preset(name: str) -> Schedule:
         # learned proposal (the network goes in Schedule.model)
         "learned": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_NONE, **both),
         "learned_threshold": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_THRS, **both),
+        # the same with the gated local-repair fallback
+        "learned_gated": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_NONE, local_gate=1, **both),
+        "learned_threshold_gated": Schedule(sk_policy=SK_LEARNED, dm_policy=DM_THRS, local_gate=1, **both),
     }
     if name not in table:
         raise KeyError(name)

@@ -72,7 +72,7 @@ typedef struct {
     int32_t K;           /* inner SK cap                                    */
     double theta_th, theta_tr;
     int32_t precision;   /* 0 = CONTRACT (binary32 scaling), 1 = PAPER      */
-    int32_t pad;
+    int32_t local_gate;  /* learned proposal: 1 = gated local-repair fallback */
     const double *model; /* learned proposal: quantised MLP parameters       */
     double mix_alpha;    /* uniform share mixed into the learned proposal    */
 } or_sched;
@@ -902,6 +902,13 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
     double mant = 1.0;
     int64_t ex = 0;
     double track = 1.0;
+    /* Learned proposal with the gated fallback: the trajectory keeps its own
+     * r, c (from the outer scaling), repairs them by Eq. (local) after a
+     * step whose sampled probability fell below theta_th or after an inner
+     * DM call, and the step after such a repair draws from the scaled
+     * proposal of Eq. (q) instead of the network. */
+    const int gate = S->sk_policy == SK_LEARNED && S->local_gate;
+    int fb = 0;
     uint64_t h = 0;
 
     for (int32_t t = 0; t < n; ++t) {
@@ -921,7 +928,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         int v_is_row = v < n;
         uint64_t W = 0;
         double S_paper = 0.0;
-        if (S->sk_policy == SK_LEARNED) {
+        if (S->sk_policy == SK_LEARNED && !fb) {
             int32_t *Lg = w->cand_L;
             for (int32_t a = 0; a < kc; ++a) {
                 int32_t y = w->cand_v[a];
@@ -936,7 +943,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
             }
             or_learned_weights(Lg, kc, S->mix_alpha, w->cand_w);
             for (int32_t a = 0; a < kc; ++a) W += w->cand_w[a];
-        } else if (prec == PREC_CONTRACT) {
+        } else if (prec == PREC_CONTRACT || S->sk_policy == SK_LEARNED) {
             float smax = 0.0f;
             float sv[1];
             (void)sv;
@@ -1020,7 +1027,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         int32_t rho = v_is_row ? v : u;
         int32_t gam = v_is_row ? u : v; /* vertex id n + j */
         double z = w->r[rho] * w->c[gam - n];
-        if (S->sk_policy == SK_LEARNED) z = (double)w->cand_w[pick] / (double)W;
+        if (S->sk_policy == SK_LEARNED && !fb) z = (double)w->cand_w[pick] / (double)W;
 
         if (path) { path[2 * t] = v; path[2 * t + 1] = u; }
         h = or_splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);
@@ -1092,6 +1099,13 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
             local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam);
             out->n_local += 1;
             if (events) events[2 * t + 1] = 1;
+        } else if (gate) {
+            fb = z < S->theta_th || run_dm;
+            if (fb) {
+                local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam);
+                out->n_local += 1;
+                if (events) events[2 * t + 1] = 1;
+            }
         }
     }
     out->alive = 1;

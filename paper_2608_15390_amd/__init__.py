@@ -12,6 +12,7 @@ current stream, the library does the work.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Dict, Optional
 
 import numpy as np
@@ -19,7 +20,8 @@ import numpy as np
 from . import _native as N
 from .inputs import SparseMatrix
 
-__all__ = ["PermEst", "PermEstBatch", "ProposalNet", "preset", "Schedule", "PermEstError"]
+__all__ = ["PermEst", "PermEstBatch", "ProposalNet", "preset", "Schedule", "PermEstError", "save_model",
+           "load_model"]
 
 PermEstError = N.PermEstError
 Schedule = N.Schedule
@@ -38,6 +40,26 @@ def preset(name: str, **overrides) -> N.Schedule:
     for k, v in overrides.items():
         setattr(s, k, v)
     return s
+
+
+def save_model(path: str, params, mix_alpha: float) -> None:
+    """Write a network (MLP_NPARAM float values, host array or tensor) and
+    its uniform share to `path` (perm_est_model_save)."""
+    if hasattr(params, "detach"):
+        params = params.detach().cpu().numpy()
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != MLP_NPARAM:
+        raise ValueError(f"expected {MLP_NPARAM} parameters")
+    N.check(N.load().perm_est_model_save(os.fsencode(path), p.ctypes.data, float(mix_alpha)))
+
+
+def load_model(path: str):
+    """(params as a float32 numpy array, mix_alpha) from a file written by
+    save_model (perm_est_model_load)."""
+    p = np.empty(MLP_NPARAM, dtype=np.float32)
+    a = C.c_double()
+    N.check(N.load().perm_est_model_load(os.fsencode(path), p.ctypes.data, C.byref(a)))
+    return p, a.value
 
 
 def _ptr(t) -> Optional[int]:

@@ -11,7 +11,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 # PERM_EST_LIBRARY selects another build of the same library (same ABI)
 LIB_PATH = os.environ.get("PERM_EST_LIBRARY") or os.path.join(_PKG, "libpermest.so")
 
-PE_OK, PE_EINVAL, PE_ENOMEM, PE_EDEVICE, PE_ENOTSUP = 0, -1, -2, -3, -4
+PE_OK, PE_EINVAL, PE_ENOMEM, PE_EDEVICE, PE_ENOTSUP, PE_EIO = 0, -1, -2, -3, -4, -5
 
 
 class Options(C.Structure):
@@ -28,7 +28,8 @@ class Schedule(C.Structure):
         ("K", C.c_int32),
         ("theta_th", C.c_double),
         ("theta_tr", C.c_double),
-        ("reserved", C.c_int32 * 4),
+        ("local_gate", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
     def as_dict(self):
@@ -56,6 +57,8 @@ class Result(C.Structure):
         ("n_local_entries", C.c_int64),
         ("n_local_values", C.c_int64),
         ("n_mlp_tiles", C.c_int64),
+        ("n_entries_scanned_v", C.c_int64),
+        ("kernel_seconds", C.c_double),
     ]
 
     def as_dict(self):
@@ -83,6 +86,8 @@ EXPORTS = [
     "perm_est_run_range",
     "perm_est_run_batch",
     "perm_est_set_model",
+    "perm_est_model_save",
+    "perm_est_model_load",
     "perm_est_record",
     "perm_est_mlp_create",
     "perm_est_mlp_get_params",
@@ -130,6 +135,10 @@ def load():
     L.perm_est_run_batch.restype = C.c_int
     L.perm_est_set_model.argtypes = [P, P, C.c_double, P]
     L.perm_est_set_model.restype = C.c_int
+    L.perm_est_model_save.argtypes = [C.c_char_p, P, C.c_double]
+    L.perm_est_model_save.restype = C.c_int
+    L.perm_est_model_load.argtypes = [C.c_char_p, P, C.POINTER(C.c_double)]
+    L.perm_est_model_load.restype = C.c_int
     L.perm_est_record.argtypes = [P, P, C.c_uint64, C.POINTER(Schedule), C.POINTER(RecordBuffers), P,
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64), P]
     L.perm_est_record.restype = C.c_int

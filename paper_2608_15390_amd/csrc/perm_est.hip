@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -110,12 +111,14 @@ struct Tune {
 
 }  // namespace
 
-constexpr int kWorkTotals = 6;  // launch-wide work counters, see BatchArgs::work_totals
+constexpr int kWorkTotals = 7;  // launch-wide work counters, see BatchArgs::work_totals
 
 struct perm_est {
     int device = 0;
     uint32_t opt_flags = 0;
     int cu_count = 256;
+    size_t lds_block = 64 * 1024;  // LDS one workgroup may allocate (queried)
+    size_t lds_cu = 160 * 1024;    // LDS of one compute unit
     std::vector<MatData> mats;
     std::vector<Tune> tunes;
     // reusable run buffers
@@ -136,6 +139,7 @@ struct perm_est {
     int32_t *tmp_counters = nullptr;
     int64_t tmp_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evk0 = nullptr, evk1 = nullptr;  // the trajectory kernel alone (eager launches)
     // learned proposal: snapped network parameters and the softmax table
     float *mlp = nullptr;
     int64_t *etab = nullptr;
@@ -417,6 +421,7 @@ void launch_traj(int sk, bool dm, bool wt, unsigned blocks, unsigned threads, si
         case PE_SK_FIXED: launch_dm<kSkFixed>(dm, wt, blocks, threads, shmem, s, b); break;
         case PE_SK_ADAPTIVE: launch_dm<kSkAdaptive>(dm, wt, blocks, threads, shmem, s, b); break;
         case PE_SK_LOCAL: launch_dm<kSkLocal>(dm, wt, blocks, threads, shmem, s, b); break;
+        case kSkLearnedGated: launch_dm<kSkLearnedGated>(dm, wt, blocks, threads, shmem, s, b); break;
         default: launch_dm<kSkLearned>(dm, wt, blocks, threads, shmem, s, b); break;
     }
 }
@@ -434,6 +439,7 @@ const void *traj_kernel_fn(int sk, bool dm, bool wt) {
         case PE_SK_FIXED: return kernel_dm<kSkFixed>(dm, wt);
         case PE_SK_ADAPTIVE: return kernel_dm<kSkAdaptive>(dm, wt);
         case PE_SK_LOCAL: return kernel_dm<kSkLocal>(dm, wt);
+        case kSkLearnedGated: return kernel_dm<kSkLearnedGated>(dm, wt);
         default: return kernel_dm<kSkLearned>(dm, wt);
     }
 }
@@ -461,7 +467,10 @@ int check_schedule(const perm_est_schedule *s) {
     if (s->initial_dm < 0 || s->initial_dm > 1) return fail(PE_EINVAL, "bad initial_dm");
     if (s->K0 < 0 || s->K < 0) return fail(PE_EINVAL, "K0 and K must be >= 0");
     if (!std::isfinite(s->theta_th) || !std::isfinite(s->theta_tr)) return fail(PE_EINVAL, "bad thresholds");
-    for (int i = 0; i < 4; ++i)
+    if (s->local_gate < 0 || s->local_gate > 1) return fail(PE_EINVAL, "bad local_gate");
+    if (s->local_gate && s->sk_policy != PE_SK_LEARNED)
+        return fail(PE_EINVAL, "local_gate applies to the learned proposal only");
+    for (int i = 0; i < 3; ++i)
         if (s->reserved[i] != 0) return fail(PE_EINVAL, "reserved schedule fields must be 0");
     return PE_OK;
 }
@@ -501,11 +510,17 @@ int make_matrix(perm_est *h, int32_t n, int64_t nnz, const int32_t *row_ptr, con
     if (hipMemset(h->flags, 0, sizeof(int32_t)) != hipSuccess) return fail(PE_EDEVICE, "hipMemset failed");
     k_csc2csr<<<blocks_for(n), 256>>>(n, M.row_ptr, M.col_idx, M.col_ptr, M.row_idx, M.csc2csr, h->flags);
     k_edge_row<<<blocks_for(n), 256>>>(n, M.row_ptr, M.edge_row);
-    if (values) k_gather_f32<<<blocks_for(nnz), 256>>>(nnz, M.val, M.csc2csr, M.val_csc);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpy(&err, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(PE_EDEVICE, "edge map kernel failed");
+    // the map has an entry for every CSC position only when both forms agree;
+    // the value gather reads through it, so it runs after the check
     if (err) return fail(PE_EINVAL, "CSR and CSC hold different entries");
+    if (values) {
+        k_gather_f32<<<blocks_for(nnz), 256>>>(nnz, M.val, M.csc2csr, M.val_csc);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return fail(PE_EDEVICE, "value gather kernel failed");
+    }
     return PE_OK;
 }
 
@@ -521,11 +536,16 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
+        h->lds_block = (size_t)lds;
+    h->lds_cu = std::max(h->lds_cu, h->lds_block);
     int rc;
     if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, kWorkTotals)) || (rc = dalloc(&h->flags, 8)) ||
         (rc = dalloc(&h->batch_dev, 1)) || (rc = dalloc(&h->rec_ctr, 2)))
         return rc;
-    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipEventCreate(&h->evk0) != hipSuccess || hipEventCreate(&h->evk1) != hipSuccess)
         return fail(PE_EDEVICE, "hipEventCreate failed");
     return PE_OK;
 }
@@ -576,8 +596,11 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     if ((rc = grow_mats(h, count))) return rc;
     const bool learned = sched->sk_policy == PE_SK_LEARNED;
     if (learned && !h->has_model) return fail(PE_EINVAL, "PE_SK_LEARNED needs perm_est_set_model first");
-    const bool own_rc = sched->sk_policy != PE_SK_NONE && !learned;
-    const bool local = sched->sk_policy == PE_SK_LOCAL;
+    // the gated fallback keeps its own scaling values and repairs them locally
+    const bool gated = learned && sched->local_gate;
+    const int sk_kind = gated ? kSkLearnedGated : sched->sk_policy;
+    const bool own_rc = (sched->sk_policy != PE_SK_NONE && !learned) || gated;
+    const bool local = sched->sk_policy == PE_SK_LOCAL || gated;
     const bool dm = sched->dm_policy != PE_DM_NONE;
     const bool wt = h->mats[0].weighted;
     for (auto &M : h->mats)
@@ -645,7 +668,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.sk_policy = sched->sk_policy;
         a.dm_policy = sched->dm_policy;
         a.K = sched->K;
-        a.scaled = !learned && ((P->r0 != nullptr) || own_rc);
+        a.scaled = gated || (!learned && ((P->r0 != nullptr) || own_rc));
         a.theta_th = sched->theta_th;
         a.theta_tr = sched->theta_tr;
         a.seed = seed;
@@ -691,7 +714,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
 
     // ---- tier and launch shape
     const size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
-    const size_t kLdsBlock = 64 * 1024, kLdsCU = 160 * 1024;
+    const size_t kLdsBlock = h->lds_block, kLdsCU = h->lds_cu;
     // per-matrix tier: a matrix whose state fits beside the tree in 32 KB runs
     // in LDS, unless such matrices carry under half of the launch's work (then
     // reserving their LDS would only cost the others occupancy)
@@ -729,11 +752,14 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     // four trajectories per wave (16-lane rows) for a single large matrix
     // under the plain estimator: short candidate lists leave most of a wave
     // idle, so rows give 4x the parallelism per wave
+    const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
+    // (a wave of rows holds four trees; when even one such wave does not fit
+    // a block's LDS, the matrix runs one trajectory per wave instead)
     const bool rows = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD &&
                       sched->sk_policy == PE_SK_NONE && hbm_cap > 0 && !parts[0].path &&
-                      !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY);
+                      !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY) &&
+                      block_fixed + 4 * tree_bytes + (size_t)lds_cap <= kLdsBlock;
     const int tpw = rows ? 4 : 1;  // trajectories per wave
-    const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     size_t per_wave = (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
     int wpb = wpb_req > 0 ? wpb_req : 4;
     if (rows && wpb_req <= 0) {
@@ -762,7 +788,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     } else {
         // as many resident blocks as registers and LDS allow, up to the cap
         int nb = 0;
-        const void *kfn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
+        const void *kfn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sk_kind, dm, wt);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, wpb * kWave, shmem) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = std::max(1, 16 / wpb);
@@ -794,21 +820,23 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipMemcpyAsync(h->seg_dev, h->seg_host.data(), sizeof(ReduceSeg) * count, hipMemcpyHostToDevice, s));
     PE_HIP(hipMemcpyAsync(h->batch_dev, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
     // the launch sequence; counters are cleared by kernels (no memset nodes)
-    auto enqueue = [&](hipStream_t q) -> int {
+    auto enqueue = [&](hipStream_t q, bool kernel_events) -> int {
         k_set_u32<<<1, 1, 0, q>>>(h->work, 0u);
         k_set_u32<<<1, 1, 0, q>>>(h->work + 1, 0u);
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
+        if (kernel_events) PE_HIP(hipEventRecord(h->evk0, q));
         if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
-        else launch_traj(sched->sk_policy, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
+        else launch_traj(sk_kind, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
         PE_HIP(hipGetLastError());
+        if (kernel_events) PE_HIP(hipEventRecord(h->evk1, q));
         // per-matrix statistics over each matrix's slice of the outputs
         if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(h->seg_dev, h->stats);
         PE_HIP(hipGetLastError());
         return PE_OK;
     };
     if (graph && !rec) {
-        const void *fn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sched->sk_policy, dm, wt);
+        const void *fn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sk_kind, dm, wt);
         const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
                           h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
                           h->graph_res == (res != nullptr);
@@ -817,7 +845,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
             if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
             if (!h->cap_stream) PE_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
             PE_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            const int erc = enqueue(h->cap_stream);
+            const int erc = enqueue(h->cap_stream, false);
             hipGraph_t g = nullptr;
             const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
             if (erc) { if (g) (void)hipGraphDestroy(g); return erc; }
@@ -834,7 +862,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         PE_HIP(hipGraphLaunch(h->graph_exec, s));
     } else {
         PE_HIP(hipEventRecord(h->ev0, s));
-        if ((rc = enqueue(s))) return rc;
+        if ((rc = enqueue(s, true))) return rc;
     }
     PE_HIP(hipEventRecord(h->ev1, s));
     std::vector<DevStats> st(count);
@@ -844,8 +872,10 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipMemcpyAsync(wt_tot, h->work_totals, sizeof(wt_tot), hipMemcpyDeviceToHost, s));
     PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
-    float ms = 0.0f;
+    float ms = 0.0f, kms = 0.0f;
     PE_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (graph && !rec) kms = ms;  // a replayed graph is timed as a whole
+    else PE_HIP(hipEventElapsedTime(&kms, h->evk0, h->evk1));
     if (elapsed_ms) *elapsed_ms = ms;
     if (err_bits)
         return fail(PE_EDEVICE, "trajectory kernel reported an internal inconsistency (bits " +
@@ -873,6 +903,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
             r.n_local_entries = (int64_t)wt_tot[2];
             r.n_local_values = (int64_t)wt_tot[3];
             r.n_mlp_tiles = (int64_t)wt_tot[5];
+            r.n_entries_scanned_v = (int64_t)wt_tot[6];
+            r.kernel_seconds = kms * 1e-3;
         }
     }
     return PE_OK;
@@ -884,8 +916,9 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
 int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, const std::vector<RunPart> &parts,
                 hipStream_t s, int *wpb, int *per_cu) {
     const int force = (h->opt_flags & PE_FLAG_FORCE_HBM) ? 1 : 0;
+    const int sk_kind = (sched->sk_policy == PE_SK_LEARNED && sched->local_gate) ? kSkLearnedGated : sched->sk_policy;
     for (auto &t : h->tunes)
-        if (t.sk == sched->sk_policy && t.dm == (sched->dm_policy != 0) && t.force_hbm == force) {
+        if (t.sk == sk_kind && t.dm == (sched->dm_policy != 0) && t.force_hbm == force) {
             *wpb = t.wpb; *per_cu = t.per_cu;
             return PE_OK;
         }
@@ -902,7 +935,7 @@ int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, cons
     const int cand_cu[] = {4, 8, 16};
     double best = 1e300;
     Tune tb;
-    tb.sk = sched->sk_policy; tb.dm = sched->dm_policy != 0; tb.force_hbm = force;
+    tb.sk = sk_kind; tb.dm = sched->dm_policy != 0; tb.force_hbm = force;
     for (int w : cand_wpb)
         for (int c : cand_cu) {
             const int per_cu_blocks = std::max(1, c / w);
@@ -1099,6 +1132,12 @@ int perm_est_schedule_preset(const char *name, perm_est_schedule *out) {
         paper(PE_SK_LEARNED, PE_DM_NONE);
     } else if (nm == "learned_threshold") {
         paper(PE_SK_LEARNED, PE_DM_THRS);
+    } else if (nm == "learned_gated") {
+        paper(PE_SK_LEARNED, PE_DM_NONE);
+        s.local_gate = 1;
+    } else if (nm == "learned_threshold_gated") {
+        paper(PE_SK_LEARNED, PE_DM_THRS);
+        s.local_gate = 1;
     } else {
         return fail(PE_EINVAL, "unknown preset '" + nm + "'");
     }
@@ -1163,6 +1202,8 @@ void perm_est_destroy(perm_est_t *h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->evk0) (void)hipEventDestroy(h->evk0);
+    if (h->evk1) (void)hipEventDestroy(h->evk1);
     delete h;
 }
 
@@ -1237,6 +1278,73 @@ int perm_est_set_model(perm_est_t *h, const float *params, double mix_alpha, voi
     }
     h->mix_alpha = mix_alpha;
     h->has_model = true;
+    return PE_OK;
+}
+
+// ---- model files: "PEMLP001", u32 parameter count, u32 0, f64 alpha,
+// f32 parameters, u64 FNV-1a of everything before it (all little-endian)
+namespace {
+constexpr char kModelMagic[8] = {'P', 'E', 'M', 'L', 'P', '0', '0', '1'};
+constexpr size_t kModelBytes = 8 + 4 + 4 + 8 + 4 * (size_t)kNParam;
+
+uint64_t fnv1a64(const unsigned char *p, size_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+}  // namespace
+
+int perm_est_model_save(const char *path, const float *params, double mix_alpha) {
+    if (!path || !params) return fail(PE_EINVAL, "null path or params");
+    if (!(mix_alpha >= 0.0 && mix_alpha <= 1.0)) return fail(PE_EINVAL, "mix_alpha must lie in [0, 1]");
+    for (int i = 0; i < kNParam; ++i)
+        if (!std::isfinite(params[i])) return fail(PE_EINVAL, "params hold a non-finite value");
+    std::vector<unsigned char> buf(kModelBytes + 8);
+    unsigned char *q = buf.data();
+    const uint32_t np = (uint32_t)kNParam, zero = 0;
+    std::memcpy(q, kModelMagic, 8);
+    std::memcpy(q + 8, &np, 4);
+    std::memcpy(q + 12, &zero, 4);
+    std::memcpy(q + 16, &mix_alpha, 8);
+    std::memcpy(q + 24, params, 4 * (size_t)kNParam);
+    const uint64_t h = fnv1a64(q, kModelBytes);
+    std::memcpy(q + kModelBytes, &h, 8);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(PE_EIO, std::string("cannot open for writing: ") + path);
+    const bool ok = std::fwrite(q, 1, buf.size(), f) == buf.size();
+    if (std::fclose(f) != 0 || !ok) return fail(PE_EIO, std::string("write failed: ") + path);
+    return PE_OK;
+}
+
+int perm_est_model_load(const char *path, float *params, double *mix_alpha) {
+    if (!path || !params || !mix_alpha) return fail(PE_EINVAL, "null path, params or mix_alpha");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PE_EIO, std::string("cannot open for reading: ") + path);
+    std::vector<unsigned char> buf(kModelBytes + 9);
+    const size_t got = std::fread(buf.data(), 1, buf.size(), f);
+    std::fclose(f);
+    if (got != kModelBytes + 8) return fail(PE_EINVAL, "model file has the wrong size");
+    const unsigned char *q = buf.data();
+    uint32_t np = 0, zero = 1;
+    uint64_t h = 0;
+    double alpha = 0.0;
+    std::memcpy(&np, q + 8, 4);
+    std::memcpy(&zero, q + 12, 4);
+    std::memcpy(&alpha, q + 16, 8);
+    std::memcpy(&h, q + kModelBytes, 8);
+    if (std::memcmp(q, kModelMagic, 8) != 0 || np != (uint32_t)kNParam || zero != 0)
+        return fail(PE_EINVAL, "not a model file of this network");
+    if (fnv1a64(q, kModelBytes) != h) return fail(PE_EINVAL, "model file checksum mismatch");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(PE_EINVAL, "model file holds a bad mix_alpha");
+    std::vector<float> p(kNParam);
+    std::memcpy(p.data(), q + 24, 4 * (size_t)kNParam);
+    for (int i = 0; i < kNParam; ++i)
+        if (!std::isfinite(p[i])) return fail(PE_EINVAL, "model file holds a non-finite value");
+    std::memcpy(params, p.data(), 4 * (size_t)kNParam);
+    *mix_alpha = alpha;
     return PE_OK;
 }
 

@@ -33,7 +33,10 @@ __global__ void k_edge_row(int32_t n, const int32_t *row_ptr, int32_t *edge_row)
 
 __global__ void k_gather_f32(int64_t m, const float *src, const int32_t *idx, float *dst) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < m) dst[p] = src[idx[p]];
+    if (p < m) {
+        const int32_t q = idx[p];
+        if (q >= 0) dst[p] = src[q];
+    }
 }
 
 __global__ void k_fill_i32(int64_t cnt, int32_t *p, int32_t v) {

@@ -522,6 +522,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 }
                 if (rl == 0) {
                     work.scan += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
+                    work.scan_v += (uint64_t)(ve - vb);
                     work.dec += (uint64_t)(kc - 1 + kb);
                 }
                 wave_fence();
@@ -567,6 +568,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
     if (rl == 0 && B.work_totals) {
         atomicAdd(B.work_totals + 0, (unsigned long long)work.scan);
         atomicAdd(B.work_totals + 1, (unsigned long long)work.dec);
+        atomicAdd(B.work_totals + 6, (unsigned long long)work.scan_v);
     }
 }
 

@@ -62,7 +62,11 @@ struct Rec {
     int32_t stamp;  // (step + 1) << 6 | lane of the last local-repair visit
 };
 
-enum : int32_t { kSkNone = 0, kSkFixed = 1, kSkAdaptive = 2, kSkLocal = 3, kSkLearned = 4 };
+// kSkLearnedGated: the learned proposal with the gated local-repair fallback
+// (own scaling values, Eq. (local) after a low-probability step or an inner
+// DM call, the scaled proposal of Eq. (q) on the step after such a repair)
+enum : int32_t { kSkNone = 0, kSkFixed = 1, kSkAdaptive = 2, kSkLocal = 3, kSkLearned = 4, kSkLearnedGated = 5 };
+__host__ __device__ constexpr bool learned_kind(int sk) { return sk == kSkLearned || sk == kSkLearnedGated; }
 enum : int32_t { kDmNone = 0, kDmAll = 1, kDmThrs = 2, kDmTrck = 3 };
 
 struct TrajArgs {
@@ -495,6 +499,7 @@ struct Work {
     uint64_t loc_values = 0;  // scaling values recomputed by local repairs
     uint64_t sweeps = 0;      // full SK iterations
     uint64_t mlp_tiles = 0;   // 16-candidate tiles through the proposal network
+    uint64_t scan_v = 0;      // adjacency entries read at the selected vertex
 };
 
 __device__ __forceinline__ uint64_t lemire_from(uint64_t x, uint64_t W, uint64_t seed, uint32_t k,
@@ -733,7 +738,9 @@ __device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int3
 
 // ------------------------------------------------------------------ kernel
 template <int SK>
-struct OwnRC { static constexpr bool value = SK == kSkFixed || SK == kSkAdaptive || SK == kSkLocal; };
+struct OwnRC {
+    static constexpr bool value = SK == kSkFixed || SK == kSkAdaptive || SK == kSkLocal || SK == kSkLearnedGated;
+};
 
 // Features of the candidate edge of Eq. (q) for the learned proposal. The
 // definition (the oracle's) is FP64: Q(y) = clamp(rint(64 y), -256, 255) / 64
@@ -995,8 +1002,10 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
     bool alive = a.ok0 != 0;
 
     int32_t k4 = 0;  // learned feature x4: rint(64 t / n)
+    bool fb = false;  // gated fallback: this step draws from the scaled proposal
     for (int32_t t = 0; alive && t < n; ++t) {
         k4 = advance_t_grid(k4, t, n);
+        const bool net = learned_kind(SK) && !fb;  // the network proposes this step
         // ---- choose the vertex
         int32_t v = -1, gsel = -1;
         int32_t vb = 0, ve = 0;
@@ -1035,7 +1044,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             if (p < ve) {
                 T.entry(v_row, p, cy, e, bv);
                 cd = T.deg[cy];
-                if (a.scaled) sc = T.scale(cy);
+                if (a.scaled && !net) sc = T.scale(cy);
                 T.list(cy, cub, cue);  // issued with the degree load; u's list comes from here
                 cand = cd != kRetired && !T.removed(e);
             }
@@ -1043,7 +1052,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             if (kc == 0) { alive = false; break; }
             const float s = a.scaled ? bv * sc : bv;
             uint64_t w = 0;
-            if (SK == kSkLearned) {
+            if (net) {
                 // quantised network logits -> integer softmax table -> uniform mix
                 const uint32_t deg_v = (uint32_t)kc;
                 const int32_t rho_c = v_row ? v : cy, gam_c = v_row ? cy : v;
@@ -1176,7 +1185,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             // learned: logits of every candidate chunk into lst_b (free here)
             int32_t lmx = -2147483647;
             int64_t Ssum = 0;
-            if (SK == kSkLearned && kc > 1) {
+            if (net && kc > 1) {
                 int32_t idx0 = 0;
                 for (int32_t base = vb; base < ve; base += kWave) {
                     const int32_t p = base + l;
@@ -1217,7 +1226,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             }
             // ci: the candidate's rank among all candidates (learned logits in lst_b)
             auto weight_of = [&](int32_t y, float bv, int32_t ci) -> uint64_t {
-                if (SK == kSkLearned) {
+                if (net) {
                     if (kc == 1) return 1ull;
                     const int32_t d = lmx - T.lst_b[ci];
                     const int64_t E = d < kEtabLds ? (int64_t)etab[d] : 0;
@@ -1302,7 +1311,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         }
         const int32_t rho = v_row ? v : u;
         const int32_t gam = v_row ? u : v;  // column vertex id
-        const double z = SK == kSkLearned ? (double)w_u / (double)W : (double)T.scale(rho) * (double)T.scale(gam);
+        const double z = net ? (double)w_u / (double)W : (double)T.scale(rho) * (double)T.scale(gam);
         if (path && l == 0) { path[2 * t] = v; path[2 * t + 1] = u; }
         h = splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);
 
@@ -1310,7 +1319,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         int32_t ub, ue;
         // learned: u's list, its neighbours and their degrees were read for
         // the features (nothing has changed since); move them into place
-        const bool from_cache = SK == kSkLearned && nc.valid && u_lane >= 0;
+        const bool from_cache = net && nc.valid && u_lane >= 0;
         int32_t u_off = 0;
         if (from_cache) u_off = read_lane(nc.off, u_lane);
         if (u_lane >= 0) {
@@ -1394,6 +1403,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             }
         }
         work.scan += (uint64_t)(ve - vb) + (uint64_t)(ue - ub);
+        work.scan_v += (uint64_t)(ve - vb);
         work.dec += (uint64_t)(kc - 1 + kb);
         wave_fence();
         // refresh the group of v from the leaves read at selection time
@@ -1443,6 +1453,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         if (!next_select_checks && T.global_min() == 0) { alive = false; break; }
 
         // ---- P_DM: support filtering of the child
+        bool ran_dm = false;
         if (DM) {
             bool run_dm = false;
             if (a.dm_policy == kDmAll) run_dm = true;
@@ -1457,6 +1468,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 if (!ok) { alive = false; break; }
                 T.dm_apply();
                 track = 1.0;
+                ran_dm = true;
             }
         }
 
@@ -1472,27 +1484,37 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             for (int it = 0; it < nit; ++it) T.sk_sweep();
             n_sweeps += nit;
             work.sweeps += (uint64_t)nit;
-        } else if (SK == kSkLocal) {
-            // rho_list = N_t(rho)\{gam} (columns), gam_list = N_t(gam)\{rho} (rows)
-            if (fast_v && fast_u) {
-                const int32_t other_v = (cand && cy != u) ? cy : -1;
-                const int32_t other_u = take ? by : -1;
-                if (v_row) local_repair_lanes(T, other_v, other_u, t, work);
-                else local_repair_lanes(T, other_u, other_v, t, work);
-            } else {
-                if (fast_v) {
-                    const uint64_t msk = ballot(cand);
-                    if (cand) T.lst_a[rank_below(msk)] = cy;
-                }
-                if (fast_u) {
-                    const uint64_t msk = ballot(take);
-                    if (take) T.lst_b[rank_below(msk)] = by;
-                }
-                wave_fence();
-                if (v_row) local_repair_lists(T, T.lst_a, kc, u, T.lst_b, kb, -1, t, work);
-                else local_repair_lists(T, T.lst_b, kb, -1, T.lst_a, kc, u, t, work);
+        } else if (SK == kSkLocal || SK == kSkLearnedGated) {
+            // Local: every step.  Gated learned: after a step whose sampled
+            // probability fell below theta_th or after inner DM, and then the
+            // next step draws from the scaled proposal.
+            bool repair = true;
+            if (SK == kSkLearnedGated) {
+                repair = z < a.theta_th || ran_dm;
+                fb = repair;
             }
-            n_local += 1;
+            if (repair) {
+                // rho_list = N_t(rho)\{gam} (columns), gam_list = N_t(gam)\{rho} (rows)
+                if (fast_v && fast_u) {
+                    const int32_t other_v = (cand && cy != u) ? cy : -1;
+                    const int32_t other_u = take ? by : -1;
+                    if (v_row) local_repair_lanes(T, other_v, other_u, t, work);
+                    else local_repair_lanes(T, other_u, other_v, t, work);
+                } else {
+                    if (fast_v) {
+                        const uint64_t msk = ballot(cand);
+                        if (cand) T.lst_a[rank_below(msk)] = cy;
+                    }
+                    if (fast_u) {
+                        const uint64_t msk = ballot(take);
+                        if (take) T.lst_b[rank_below(msk)] = by;
+                    }
+                    wave_fence();
+                    if (v_row) local_repair_lists(T, T.lst_a, kc, u, T.lst_b, kb, -1, t, work);
+                    else local_repair_lists(T, T.lst_b, kb, -1, T.lst_a, kc, u, t, work);
+                }
+                n_local += 1;
+            }
         }
     }
 
@@ -1520,7 +1542,8 @@ struct BatchArgs {
     int32_t count;
     int64_t total;
     uint32_t *work_next;      // item counter (zeroed before launch)
-    unsigned long long *work_totals;  // [6]: scanned, decrements, local entries, local values, sweeps, tiles
+    unsigned long long *work_totals;  // [7]: scanned, decrements, local entries, local values, sweeps,
+                                      // tiles, scanned at the selected vertex
     char *hbm_state;          // base of the per-wave HBM slots, or nullptr if every matrix is LDS tier
     uint64_t hbm_stride;
     int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
@@ -1545,8 +1568,8 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
     // block: [network weights (learned)] then per wave [tree | network tiles | state]
     LearnedLds *lrn = reinterpret_cast<LearnedLds *>(smem);
     MlpLds *mlpw = &lrn->net;
-    char *waves = smem + (SK == kSkLearned ? kMlpBlockBytes : 0);
-    if (SK == kSkLearned) {
+    char *waves = smem + (learned_kind(SK) ? kMlpBlockBytes : 0);
+    if (learned_kind(SK)) {
         stage_weights<true>(mlpw, B.mlp);
         for (int i = threadIdx.x; i < kEtabLds; i += blockDim.x) lrn->etab[i] = (uint32_t)B.etab[i];
         __syncthreads();
@@ -1589,6 +1612,7 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
         atomicAdd(B.work_totals + 3, (unsigned long long)work.loc_values);
         atomicAdd(B.work_totals + 4, (unsigned long long)work.sweeps);
         atomicAdd(B.work_totals + 5, (unsigned long long)work.mlp_tiles);
+        atomicAdd(B.work_totals + 6, (unsigned long long)work.scan_v);
     }
 }
 

@@ -62,3 +62,48 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_pooled_statistics_match_the_oracle():
+    lw, al = _sample(3000, 3)
+    st = O.stats(lw, al.astype(np.uint8))
+    r = bench.pooled(lw, al, 1.0)
+    for k in ("log_estimate", "ess", "rse", "var_logw", "p_match"):
+        assert r[k] == pytest.approx(st[k], rel=1e-10), k
+
+
+def test_pooling_launch_results_equals_the_union():
+    """ESS of the whole job pooled from per-launch statistics (disjoint id
+    ranges) equals the ESS of the union, not the sum of per-launch ESS."""
+    lw, al = _sample(4000, 4)
+    lw[7] = 40.0  # one dominant weight: per-launch ESS near 1 in its launch
+    al[7] = True
+    parts = []
+    for a in range(0, 4000, 500):
+        st = O.stats(lw[a:a + 500], al[a:a + 500].astype(np.uint8))
+        st["n_traj"] = 500
+        parts.append(st)
+    union = bench.pooled(lw, al, 1.0)["ess"]
+    assert bench.pool_results(parts) == pytest.approx(union, rel=1e-9)
+    assert sum(p["ess"] for p in parts) > 3 * union
+
+
+def test_byte_model_unit_costs():
+    """The per-unit figures of the byte model, one unit at a time."""
+    z = dict(n_steps=0, n_entries_scanned=0, n_entries_scanned_v=0, n_decrements=0, n_traj=0,
+             n_local_entries=0, n_local_values=0, n_full_sk=0, n_dm=0)
+
+    def one(**kw):
+        d = dict(z)
+        d.update(kw)
+        return bench.algorithmic_bytes(d, 10, 30, scaled=True)
+
+    assert one(n_entries_scanned=1) == 5
+    assert one(n_entries_scanned_v=1) == 4
+    assert one(n_decrements=1) == 36 + 28
+    assert one(n_steps=1) == 4 * 28
+    assert one(n_traj=1) == 24 * 10 + 9
+    assert one(n_local_entries=1) == 9 and one(n_local_values=1) == 4
+    assert one(n_full_sk=1) == 18 * 30 + 16 * 10 and one(n_dm=1) == 27 * 30
+    d = dict(z, n_entries_scanned_v=1)
+    assert bench.algorithmic_bytes(d, 10, 30, scaled=False) == 0

@@ -1,0 +1,94 @@
+"""Parity at the large sizes, in the launch shapes the benchmark uses.
+
+* The learned proposal on the n = 1e5, average-degree-8 workload: one
+  benchmark step (5000 trajectory ids in one launch) with sampled ids
+  recomputed one by one by the oracle.
+* One matrix of order 6e5, where the min-tree over 2n degree leaves needs
+  three levels (more than 64 x 64 groups of 256 leaves): the plain
+  estimator (its default four-trajectories-per-wave launch and whole
+  waves), the local repair and the learned proposal, on a planted uniform
+  matrix and on a power-law one (degrees up to 200).
+
+Paths, alive flags, counters and path hashes compare bit for bit, ln X to
+1e-12 relative (the oracle's stated FP64 agreement)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import mlp as R
+from oracle import oracle as O
+from paper_2608_15390_amd import inputs as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _osched(g, model=None, mix_alpha=0.05):
+    return O.Schedule(vertex_rule=g.vertex_rule, sk_policy=g.sk_policy, dm_policy=g.dm_policy,
+                      initial_dm=g.initial_dm, K0=g.K0, K=g.K, theta_th=g.theta_th, theta_tr=g.theta_tr,
+                      model=model, mix_alpha=mix_alpha)
+
+
+def _check_sampled(M, sched, osch, seed, first, count, picks, model=None, alpha=0.01, **flags):
+    """One GPU launch of ids first..first+count-1; the ids `picks` of it
+    recomputed by the oracle one at a time."""
+    import paper_2608_15390_amd as P
+    print(f"[gpu] n={M.n} nnz={M.nnz} sched={sched.as_dict()} ids={first}+{count} picks={picks} "
+          f"flags={flags}", flush=True)
+    est = P.PermEst(M, **flags)
+    if model is not None:
+        est.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), alpha)
+    out = est.run(first, count, seed, sched, want_hash=True, want_counters=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+    est.close()
+    A = O.OMatrix(M)
+    pre = O.prep(A, osch)
+    for k in picks:
+        o = O.run(A, osch, seed=seed, first=k, count=1, pre=pre)
+        i = k - first
+        assert g["alive"][i] == o["alive"][0], k
+        np.testing.assert_array_equal(g["counters"][i], o["counters"][0], err_msg=str(k))
+        assert g["path_hash"].view(np.uint64)[i] == o["path_hash"][0], k
+        if o["alive"][0]:
+            assert g["logw"][i] == pytest.approx(o["logw"][0], rel=1e-12, abs=0), k
+        else:
+            assert np.isneginf(g["logw"][i]), k
+    return g
+
+
+@pytest.mark.timeout(600)
+def test_learned_headline_workload_benchmark_launch():
+    """n = 1e5, avg degree 8, learned proposal (quantised network, uniform
+    share 0.01 as in the benchmark): one benchmark step of 5000 ids."""
+    import paper_2608_15390_amd as P
+    M = G.config_large(1)
+    model = R.quantize(R.init(31, scale=1.5))
+    sched = P.preset("learned")
+    _check_sampled(M, sched, _osched(sched, model, 0.01), 1, 0, 5000, [0, 2500, 4999], model=model)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,flags", [("plain", {}), ("plain", {"wave_per_trajectory": True}),
+                                        ("local_nodm", {}), ("learned", {})])
+def test_three_level_min_tree_planted_uniform(name, flags):
+    """Order 6e5 (three min-tree levels), planted permutation + 7n entries."""
+    import paper_2608_15390_amd as P
+    M = G.planted_uniform(600_000, 4_200_000, 23)
+    sched = P.preset(name)
+    model = R.quantize(R.init(31, scale=1.5)) if name == "learned" else None
+    count = 1 if name == "local_nodm" else 2
+    _check_sampled(M, sched, _osched(sched, model, 0.01), 3, 5, count, list(range(5, 5 + count)),
+                   model=model, **flags)
+
+
+@pytest.mark.timeout(600)
+def test_three_level_min_tree_power_law_learned():
+    """Order 6e5, power-law row degrees (exponent 2.5 on [2, 200]) plus a
+    planted permutation, learned proposal."""
+    import paper_2608_15390_amd as P
+    M = G.power_law(600_000, 77)
+    sched = P.preset("learned")
+    model = R.quantize(R.init(32, scale=1.5))
+    _check_sampled(M, sched, _osched(sched, model, 0.01), 4, 11, 2, [11, 12], model=model)

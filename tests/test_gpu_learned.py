@@ -163,7 +163,7 @@ def test_training_is_independent_of_the_recording_order():
 def _osched(g, model=None, mix_alpha=0.05):
     return O.Schedule(vertex_rule=g.vertex_rule, sk_policy=g.sk_policy, dm_policy=g.dm_policy,
                       initial_dm=g.initial_dm, K0=g.K0, K=g.K, theta_th=g.theta_th, theta_tr=g.theta_tr,
-                      model=model, mix_alpha=mix_alpha)
+                      model=model, mix_alpha=mix_alpha, local_gate=g.local_gate)
 
 
 def _learned_mats():
@@ -176,7 +176,8 @@ def _learned_mats():
 
 
 @pytest.mark.parametrize("name,alpha", [("learned", 0.05), ("learned_threshold", 0.05), ("learned", 0.0),
-                                        ("learned", 1.0)])
+                                        ("learned", 1.0), ("learned_gated", 0.05),
+                                        ("learned_threshold_gated", 0.05)])
 def test_learned_trajectories_match_oracle(name, alpha):
     import paper_2608_15390_amd as P
     mats = _learned_mats()
@@ -188,6 +189,8 @@ def test_learned_trajectories_match_oracle(name, alpha):
     bt.set_model(_dev(model, torch.float32), alpha)
     out = bt.run(counts, 21, sched, want_hash=True)
     torch.cuda.synchronize()
+    if sched.local_gate:  # the fallback fired and both tiers were exercised
+        assert sum(r["n_local_sk"] for r in out["results"][:1]) > 0
     lw = out["logw"].cpu().numpy()
     al = out["alive"].cpu().numpy()
     ph = out["path_hash"].cpu().numpy().view(np.uint64)

@@ -262,3 +262,88 @@ def test_feature_definitions_have_exact_integer_forms():
             q, r = divmod(64 * t, n)
             k = q + (1 if (2 * r > n or (2 * r == n and q & 1)) else 0)
             assert x[4] == clamp(k) / 64.0, (t, n)
+
+
+# ------------------------------------------- learned proposal, gated fallback
+def _gated(model, **kw):
+    return _learned(model, local_gate=1, mix_alpha=0.05, **kw)
+
+
+@pytest.mark.parametrize("dm", [O.DM_NONE, O.DM_THRS])
+@pytest.mark.parametrize("initial_dm", [0, 1])
+def test_gated_fallback_enumeration_is_exact(initial_dm, dm):
+    """The fallback only changes which positive proposal a step samples
+    from, and the weight still divides by the probability sampled, so
+    E[X] = per(A) exactly (Sec. 2) with the gate on."""
+    model = R.quantize(R.init(11, scale=2.0))
+    sched = _gated(model, initial_dm=initial_dm, K0=20 if initial_dm else 0, dm_policy=dm, theta_th=0.45)
+    g = np.random.default_rng(13 + dm)
+    fired = 0
+    for t in range(10):
+        n = int(g.integers(2, 8))
+        M = G.planted_bernoulli(n, float(g.uniform(0.2, 0.7)), int(g.integers(1 << 30)), planted="random")
+        if t % 3 == 0:
+            M = G.with_weights(M, t)
+        A = O.OMatrix(M)
+        pre = O.prep(A, sched)
+        E, _, _ = enumerate_tree(A, sched, pre)
+        assert E == pytest.approx(O.ryser_f64(dense_values(M)), rel=1e-12)
+        fired += int(O.run(A, sched, seed=1, count=50, pre=pre)["counters"][:, 3].sum())
+    assert fired > 0
+
+
+def _scaled_weights_by_hand(M, o, v, cand):
+    """Integer weights of Eq. (q) from the snapshot's r, c: s = B c (row v)
+    or B r (column v) in binary32, w = max(1, rint(2^24 s / s_max))."""
+    n = M.n
+    D = dense_values(M)
+    s = []
+    for u in cand:
+        u = int(u)
+        if v < n:
+            s.append(np.float32(D[v, u - n]) * np.float32(o["c"][u - n]))
+        else:
+            s.append(np.float32(D[u, v - n]) * np.float32(o["r"][u]))
+    s = np.array(s, dtype=np.float32)
+    smax = s.max()
+    ratio = (s / smax).astype(np.float32) * np.float32(16777216.0)
+    return np.maximum(1.0, np.rint(ratio)).astype(np.float64)
+
+
+def test_gated_fallback_steps_from_their_definition():
+    """Along gated trajectories: a step right after a repair draws from the
+    scaled proposal of Eq. (q) built here from the snapshot's r, c; r and c
+    change only across a step whose sampled probability fell below
+    theta_th (the repair), and otherwise stay as they were."""
+    model = R.quantize(R.init(21, scale=2.0))
+    sched = _gated(model, initial_dm=1, K0=30, theta_th=0.4)
+    g = np.random.default_rng(5)
+    fb_checked = plain_checked = 0
+    for trial in range(8):
+        M = G.planted_bernoulli(30, 0.15, int(g.integers(1 << 30)), planted="random")
+        if trial % 2:
+            M = G.with_weights(M, trial)
+        A = O.OMatrix(M)
+        pre = O.prep(A, sched)
+        n = M.n
+        full = O.probe(A, sched, pre, seed=9, k=trial, forced=[], stop_at=-1)
+        ev = full["events"]
+        prev = None
+        for t in range(full["steps"]):
+            o = O.probe(A, sched, pre, seed=9, k=trial, forced=[], stop_at=t)
+            assert o["stopped"] == 1
+            act = o["act"].astype(bool)
+            v = int(np.argmin(np.where(act, o["deg"], 1 << 30)))
+            repaired = t > 0 and ev[2 * (t - 1) + 1] == 1
+            if prev is not None:
+                same = np.array_equal(o["r"], prev["r"]) and np.array_equal(o["c"], prev["c"])
+                if not repaired:
+                    assert same, (trial, t)
+            if repaired and len(o["cand"]) >= 2:
+                w = _scaled_weights_by_hand(M, o, v, o["cand"])
+                np.testing.assert_array_equal(o["prob"], w / w.sum())
+                fb_checked += 1
+            elif len(o["cand"]) >= 2:
+                plain_checked += 1
+            prev = o
+    assert fb_checked >= 5 and plain_checked >= 5

@@ -14,7 +14,9 @@ candidates. From those and the recorded path the test forms by hand:
 * run_dm = All, or Thrs with z < theta_th, or Trck with track < theta_tr
   (strict comparisons);
 * the SK count: Fixed K sweeps, Adaptive clamp(ceil((1 - z) K), 0, K),
-  Local one repair;
+  Local one repair, the learned proposal's gated fallback one repair when
+  z < theta_th or DM ran (and then z of the next step is r_rho c_gam of
+  the scaled proposal it draws from);
 
 and asserts the oracle's event record (DM on/off, SK count per step) equals
 it. A floor for the ceiling, z taken after the repair, a missing reset of
@@ -61,11 +63,13 @@ def _expected(A, sched, full, snaps):
     exp = np.zeros(2 * n, dtype=np.int32)
     zs, tracks = [], []
     track = 1.0
+    gate = sched.sk_policy == O.SK_LEARNED and sched.local_gate
+    fb = False  # this step draws from the scaled proposal (gated fallback)
     steps = full["steps"]
     for t in range(steps):
         v, u = int(path[2 * t]), int(path[2 * t + 1])
         s = snaps[t]
-        if sched.sk_policy == O.SK_LEARNED:
+        if sched.sk_policy == O.SK_LEARNED and not fb:
             z = float(s["prob"][list(s["cand"]).index(u)])
         else:
             rho, gam = (v, u) if v < n else (u, v)
@@ -91,6 +95,9 @@ def _expected(A, sched, full, snaps):
             exp[2 * t + 1] = min(max(want, 0), sched.K)
         elif sched.sk_policy == O.SK_LOCAL:
             exp[2 * t + 1] = 1
+        elif gate:
+            fb = z < sched.theta_th or run_dm
+            exp[2 * t + 1] = int(fb)
     return exp, zs, tracks
 
 
@@ -107,6 +114,11 @@ def _schedules():
         "adaptive_tracked_K0_2": O.preset("adaptive_tracked").replace(K0=2, K=7, theta_tr=0.6),
         "adaptive_threshold_K0_1": O.preset("adaptive_threshold").replace(K0=1, K=9, theta_th=0.5),
         "learned_threshold": O.preset("learned_threshold").replace(model=model, mix_alpha=0.05),
+        # learned with the gated local-repair fallback (z of a fallback step
+        # is r_rho c_gam, of a network step the sampled probability)
+        "learned_gated": O.preset("learned").replace(model=model, mix_alpha=0.05, local_gate=1, theta_th=0.4),
+        "learned_threshold_gated": O.preset("learned_threshold").replace(model=model, mix_alpha=0.05,
+                                                                         local_gate=1),
     }
 
 
@@ -130,8 +142,10 @@ def test_schedule_events_recomputed_from_snapshots(name):
             seen["nit"].update(int(x) for x in exp[1::2][: len(zs)])
             seen["z_above_1"] += sum(z > 1.0 + 1.0 / max(sched.K, 1) for z in zs)
     # the walk saw both decisions (and, for Adaptive, several sweep counts)
-    if sched.dm_policy != O.DM_ALL:
+    if sched.dm_policy not in (O.DM_ALL, O.DM_NONE):
         assert seen["dm"] > 0 and seen["no_dm"] > 0, seen
+    if sched.local_gate:
+        assert seen["nit"] == {0, 1}, seen
     if sched.sk_policy == O.SK_ADAPTIVE:
         assert len(seen["nit"]) >= 3, seen
         # the clamp at 0 was needed somewhere

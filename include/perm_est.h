@@ -197,6 +197,36 @@ int perm_est_run_range(perm_est_t *h, int64_t first, int64_t count,
                        uint64_t *path_hash, int32_t *path, int32_t *counters,
                        void *stream);
 
+/* Bytes of the per-device scratch array of perm_est_run_range_noalloc. */
+#define PE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* perm_est_run_range for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same results bit for bit, and no hipMalloc,
+ * hipFree or other allocating routine.  Everything the launch needs beyond
+ * the caller's inputs and outputs -- counters, argument blocks, the
+ * statistics, the outputs left NULL (logw, alive, counters) and the
+ * per-trajectory state slots -- lives in one static device array of
+ * PE_NOALLOC_SCRATCH_BYTES bytes per GPU, looked up when the first handle
+ * on that GPU is created and held until the process ends.  Counters are
+ * cleared by kernels on `stream` before each launch.
+ *   - The handle must hold one matrix whose preprocessing for this
+ *     schedule's (initial_dm, K0) has already run (any earlier run or
+ *     run_range call with them); otherwise PE_EINVAL.
+ *   - With large per-trajectory state (state slots in device memory) fewer
+ *     trajectories run concurrently than in perm_est_run_range: as many
+ *     slots as the scratch left after the outputs holds.
+ *   - PE_ENOTSUP when the outputs left NULL (25 bytes per trajectory at
+ *     most) or one block of state slots do not fit the scratch.
+ *   - Every call on one GPU shares its array: calls that overlap in time on
+ *     the same GPU (other threads or streams) race and must not be issued.
+ * Errors otherwise as perm_est_run_range. */
+int perm_est_run_range_noalloc(perm_est_t *h, int64_t first, int64_t count,
+                               uint64_t seed, const perm_est_schedule *sched,
+                               perm_est_result *res, double *logw, uint8_t *alive,
+                               uint64_t *path_hash, int32_t *path, int32_t *counters,
+                               void *stream);
+
 /* Create one handle holding `count` matrices (batching): matrix b is given
  * by n[b], nnz[b], row_ptr[b], col_idx[b], col_ptr[b], row_idx[b] and
  * values[b] (values may be NULL for all-0/1 input; a batch is all 0/1 or

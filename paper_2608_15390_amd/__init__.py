@@ -115,9 +115,11 @@ class PermEst(_ModelMixin):
 
     def run(self, first: int, count: int, seed: int, schedule: N.Schedule, *, want_logw=True,
             want_alive=True, want_hash=False, want_path=False, want_counters=False,
-            stream=None) -> Dict:
+            stream=None, noalloc=False) -> Dict:
         """Run trajectories first..first+count-1; returns the statistics and
-        the requested per-trajectory device tensors."""
+        the requested per-trajectory device tensors.  noalloc: through
+        perm_est_run_range_noalloc (the library allocates nothing; the
+        schedule's preprocessing must have run on this handle before)."""
         import torch
 
         dev = torch.device("cuda", self.device)
@@ -129,7 +131,8 @@ class PermEst(_ModelMixin):
         cnt = torch.empty((count, 4), dtype=torch.int32, device=dev) if want_counters else None
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         res = N.Result()
-        N.check(self._lib.perm_est_run_range(
+        fn = self._lib.perm_est_run_range_noalloc if noalloc else self._lib.perm_est_run_range
+        N.check(fn(
             self._h, first, count, C.c_uint64(seed), C.byref(schedule), C.byref(res),
             _ptr(logw), _ptr(alive), _ptr(ph), _ptr(path), _ptr(cnt), C.c_void_p(st.cuda_stream)))
         out["result"] = res.as_dict()

@@ -84,6 +84,7 @@ EXPORTS = [
     "perm_est_schedule_preset",
     "perm_est_run",
     "perm_est_run_range",
+    "perm_est_run_range_noalloc",
     "perm_est_run_batch",
     "perm_est_set_model",
     "perm_est_model_save",
@@ -128,6 +129,8 @@ def load():
     L.perm_est_run_range.argtypes = [P, C.c_int64, C.c_int64, C.c_uint64, C.POINTER(Schedule),
                                      C.POINTER(Result), P, P, P, P, P, P]
     L.perm_est_run_range.restype = C.c_int
+    L.perm_est_run_range_noalloc.argtypes = L.perm_est_run_range.argtypes
+    L.perm_est_run_range_noalloc.restype = C.c_int
     PP = C.POINTER(C.c_void_p)
     L.perm_est_create_batch.argtypes = [C.c_int32, P, P, PP, PP, PP, PP, PP, C.POINTER(Options), C.POINTER(P)]
     L.perm_est_create_batch.restype = C.c_int

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -112,6 +113,35 @@ struct Tune {
 }  // namespace
 
 constexpr int kWorkTotals = 7;  // launch-wide work counters, see BatchArgs::work_totals
+
+// Scratch of perm_est_run_range_noalloc: one array per GPU the library runs
+// on, held until the process ends.  Host code never uses this name as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device (noalloc_scratch).
+constexpr size_t kScratchBytes = (size_t)PE_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `dev` (the current device), looked up
+// the first time a handle is created on that device
+int noalloc_scratch(int dev, char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PE_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PE_OK;
+}
+}  // namespace
 
 struct perm_est {
     int device = 0;
@@ -388,6 +418,14 @@ int build_prepared(MatData *h, int32_t initial_dm, int32_t K0, hipStream_t s, Pr
     return PE_OK;
 }
 
+// the preprocessed variant for (initial_dm, K0) if it exists (never builds one)
+int find_prepared(MatData *h, int32_t initial_dm, int32_t K0, Prepared **out) {
+    for (auto &P : h->preps)
+        if (P.initial_dm == initial_dm && P.K0 == K0) { *out = &P; return PE_OK; }
+    return fail(PE_EINVAL, "this schedule's preprocessing (initial_dm, K0) has not run on the handle; "
+                           "run it once with an allocating entry point first");
+}
+
 int get_prepared(MatData *h, int32_t initial_dm, int32_t K0, hipStream_t s, Prepared **out) {
     for (auto &P : h->preps)
         if (P.initial_dm == initial_dm && P.K0 == K0) { *out = &P; return PE_OK; }
@@ -540,6 +578,8 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
         h->lds_block = (size_t)lds;
     h->lds_cu = std::max(h->lds_cu, h->lds_block);
+    char *scr = nullptr;
+    if (int rc0 = noalloc_scratch(h->device, &scr)) return rc0;
     int rc;
     if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, kWorkTotals)) || (rc = dalloc(&h->flags, 8)) ||
         (rc = dalloc(&h->batch_dev, 1)) || (rc = dalloc(&h->rec_ctr, 2)))
@@ -585,15 +625,41 @@ int grow_mats(perm_est *h, size_t count) {
     return PE_OK;
 }
 
+// Device buffers one launch writes besides its outputs: the handle's own
+// (grown on demand) or, for the no-alloc entry point, regions of the
+// library's static scratch array (fixed capacities, nothing is allocated).
+struct LaunchBufs {
+    uint32_t *work = nullptr;                   // [2] item counter, error bits
+    unsigned long long *work_totals = nullptr;  // [kWorkTotals]
+    TrajArgs *args = nullptr;                   // [count]
+    BatchArgs *batch = nullptr;                 // [1]
+    int32_t *order = nullptr;                   // [count]
+    int64_t *item_off = nullptr;                // [count + 1]
+    ReduceSeg *seg = nullptr;                   // [count]
+    DevStats *stats = nullptr;                  // [count]
+    double *tmp_logw = nullptr;                 // outputs the caller did not ask for
+    uint8_t *tmp_alive = nullptr;
+    int32_t *tmp_counters = nullptr;
+    char *hbm_state = nullptr;                  // per-wave HBM slots
+    size_t hbm_bytes = 0;                       // their capacity in bytes
+};
+
 // one persistent launch over every matrix's trajectories + per-matrix
 // reductions.  res == nullptr: only time the launch shape (wpb, per_cu);
 // outputs go to scratch buffers.  rec: training-pair recording, or nullptr.
 int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vector<RunPart> &parts,
            perm_est_result *res, hipStream_t s, int wpb_req, int per_cu_req, double *elapsed_ms,
-           const perm_est_record_buffers *rec = nullptr, bool graph = false) {
+           const perm_est_record_buffers *rec = nullptr, bool graph = false, const LaunchBufs *fixed = nullptr) {
     const size_t count = h->mats.size();
     int rc;
-    if ((rc = grow_mats(h, count))) return rc;
+    if (!fixed && (rc = grow_mats(h, count))) return rc;
+    LaunchBufs lb;
+    if (fixed) {
+        lb = *fixed;
+    } else {
+        lb.work = h->work; lb.work_totals = h->work_totals; lb.args = h->args_dev; lb.batch = h->batch_dev;
+        lb.order = h->order_dev; lb.item_off = h->item_off_dev; lb.seg = h->seg_dev; lb.stats = h->stats;
+    }
     const bool learned = sched->sk_policy == PE_SK_LEARNED;
     if (learned && !h->has_model) return fail(PE_EINVAL, "PE_SK_LEARNED needs perm_est_set_model first");
     // the gated fallback keeps its own scaling values and repairs them locally
@@ -613,14 +679,19 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     int32_t tree_total = 0;
     std::vector<uint64_t> mat_bytes(count, 0);
     for (size_t b = 0; b < count; ++b) {
-        if ((rc = get_prepared(&h->mats[b], sched->initial_dm, sched->K0, s, &prep[b]))) return rc;
+        if ((rc = fixed ? find_prepared(&h->mats[b], sched->initial_dm, sched->K0, &prep[b])
+                        : get_prepared(&h->mats[b], sched->initial_dm, sched->K0, s, &prep[b])))
+            return rc;
         total += parts[b].count;
         tree_total = std::max(tree_total, prep[b]->tree.total);
     }
     if (total > ((int64_t)1 << 32) - 1) return fail(PE_EINVAL, "too many trajectories in one launch");
     bool need_tmp = false;
     for (auto &pt : parts) need_tmp = need_tmp || !pt.logw || !pt.alive || !pt.counters;
-    if (need_tmp && (rc = grow_tmp(h, total))) return rc;
+    if (need_tmp && !fixed) {
+        if ((rc = grow_tmp(h, total))) return rc;
+        lb.tmp_logw = h->tmp_logw; lb.tmp_alive = h->tmp_alive; lb.tmp_counters = h->tmp_counters;
+    }
 
     h->args_host.assign(count, TrajArgs{});
     int64_t tmp_off = 0;
@@ -675,12 +746,12 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.b = (uint32_t)b;
         a.first = parts[b].first;
         a.count = parts[b].count;
-        a.logw = parts[b].logw ? parts[b].logw : h->tmp_logw + tmp_off;
-        a.alive = parts[b].alive ? parts[b].alive : h->tmp_alive + tmp_off;
-        a.counters = parts[b].counters ? parts[b].counters : h->tmp_counters + 4 * tmp_off;
+        a.logw = parts[b].logw ? parts[b].logw : lb.tmp_logw + tmp_off;
+        a.alive = parts[b].alive ? parts[b].alive : lb.tmp_alive + tmp_off;
+        a.counters = parts[b].counters ? parts[b].counters : lb.tmp_counters + 4 * tmp_off;
         a.path_hash = parts[b].path_hash;
         a.path = parts[b].path;
-        a.err = h->work + 1;
+        a.err = lb.work + 1;
         a.mlp = learned ? h->mlp : nullptr;
         a.etab = learned ? h->etab : nullptr;
         a.mix_alpha = h->mix_alpha;
@@ -738,13 +809,13 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     static_assert(kMlpBlockBytes % 16 == 0 && kMlpWaveBytes % 16 == 0, "LDS carve-outs keep 16-byte alignment");
     BatchArgs &B = h->batch_host;
     B = BatchArgs{};
-    B.mats = h->args_dev;
-    B.order = h->order_dev;
-    B.item_off = h->item_off_dev;
+    B.mats = lb.args;
+    B.order = lb.order;
+    B.item_off = lb.item_off;
     B.count = (int32_t)count;
     B.total = total;
-    B.work_next = h->work;
-    B.work_totals = h->work_totals;
+    B.work_next = lb.work;
+    B.work_totals = lb.work_totals;
     B.lds_tree_bytes = (int32_t)tree_bytes;
     B.lds_mlp_bytes = learned ? kMlpWaveBytes : 0;
     B.mlp = learned ? h->mlp : nullptr;
@@ -796,46 +867,58 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         per_cu = (size_t)std::max(1, std::min(nb, PE_MAX_WAVES_PER_CU / wpb));
     }
     per_cu = std::max<size_t>(1, std::min<size_t>(per_cu, kLdsCU / std::max<size_t>(shmem, 1)));
-    const unsigned blocks = (unsigned)std::max<int64_t>(
+    unsigned blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((total + (int64_t)wpb * tpw - 1) / ((int64_t)wpb * tpw), (int64_t)h->cu_count * (int64_t)per_cu));
     B.waves_per_block = wpb;
     B.lds_state_bytes = (int32_t)lds_cap;
     B.hbm_state = nullptr;
     if (hbm_cap > 0) {
-        const size_t need = (size_t)blocks * wpb * tpw * hbm_cap;
-        if (h->hbm_bytes < need) {
-            dfree(h->hbm_state);
-            h->hbm_bytes = 0;
-            if ((rc = dalloc(&h->hbm_state, need))) return rc;
-            h->hbm_bytes = need;
+        const size_t per_block = (size_t)wpb * tpw * hbm_cap;
+        if (fixed) {
+            // as many resident blocks as the fixed slot region holds
+            const size_t fit = lb.hbm_bytes / per_block;
+            if (fit < 1)
+                return fail(PE_ENOTSUP, "per-trajectory state of one block (" + std::to_string(per_block) +
+                                            " B) exceeds the scratch left for it (" + std::to_string(lb.hbm_bytes) +
+                                            " B)");
+            blocks = (unsigned)std::min<size_t>(blocks, fit);
+        } else {
+            const size_t need = (size_t)blocks * per_block;
+            if (h->hbm_bytes < need) {
+                dfree(h->hbm_state);
+                h->hbm_bytes = 0;
+                if ((rc = dalloc(&h->hbm_state, need))) return rc;
+                h->hbm_bytes = need;
+            }
+            lb.hbm_state = h->hbm_state;
         }
-        B.hbm_state = h->hbm_state;
+        B.hbm_state = lb.hbm_state;
         B.hbm_stride = hbm_cap;
     }
 
-    PE_HIP(hipMemcpyAsync(h->args_dev, h->args_host.data(), sizeof(TrajArgs) * count, hipMemcpyHostToDevice, s));
-    PE_HIP(hipMemcpyAsync(h->order_dev, h->order_host.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
-    PE_HIP(hipMemcpyAsync(h->item_off_dev, h->item_off_host.data(), sizeof(int64_t) * (count + 1),
+    PE_HIP(hipMemcpyAsync(lb.args, h->args_host.data(), sizeof(TrajArgs) * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(lb.order, h->order_host.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(lb.item_off, h->item_off_host.data(), sizeof(int64_t) * (count + 1),
                           hipMemcpyHostToDevice, s));
-    PE_HIP(hipMemcpyAsync(h->seg_dev, h->seg_host.data(), sizeof(ReduceSeg) * count, hipMemcpyHostToDevice, s));
-    PE_HIP(hipMemcpyAsync(h->batch_dev, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(lb.seg, h->seg_host.data(), sizeof(ReduceSeg) * count, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(lb.batch, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
     // the launch sequence; counters are cleared by kernels (no memset nodes)
     auto enqueue = [&](hipStream_t q, bool kernel_events) -> int {
-        k_set_u32<<<1, 1, 0, q>>>(h->work, 0u);
-        k_set_u32<<<1, 1, 0, q>>>(h->work + 1, 0u);
-        k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(h->work_totals), 0);
+        k_set_u32<<<1, 1, 0, q>>>(lb.work, 0u);
+        k_set_u32<<<1, 1, 0, q>>>(lb.work + 1, 0u);
+        k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(lb.work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
         if (kernel_events) PE_HIP(hipEventRecord(h->evk0, q));
-        if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
-        else launch_traj(sk_kind, dm, wt, blocks, wpb * kWave, shmem, q, h->batch_dev);
+        if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, lb.batch);
+        else launch_traj(sk_kind, dm, wt, blocks, wpb * kWave, shmem, q, lb.batch);
         PE_HIP(hipGetLastError());
         if (kernel_events) PE_HIP(hipEventRecord(h->evk1, q));
         // per-matrix statistics over each matrix's slice of the outputs
-        if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(h->seg_dev, h->stats);
+        if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(lb.seg, lb.stats);
         PE_HIP(hipGetLastError());
         return PE_OK;
     };
-    if (graph && !rec) {
+    if (graph && !rec && !fixed) {
         const void *fn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sk_kind, dm, wt);
         const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
                           h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
@@ -868,13 +951,13 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     std::vector<DevStats> st(count);
     uint32_t err_bits = 0;
     unsigned long long wt_tot[kWorkTotals];
-    if (res) PE_HIP(hipMemcpyAsync(st.data(), h->stats, sizeof(DevStats) * count, hipMemcpyDeviceToHost, s));
-    PE_HIP(hipMemcpyAsync(wt_tot, h->work_totals, sizeof(wt_tot), hipMemcpyDeviceToHost, s));
-    PE_HIP(hipMemcpyAsync(&err_bits, h->work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
+    if (res) PE_HIP(hipMemcpyAsync(st.data(), lb.stats, sizeof(DevStats) * count, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(wt_tot, lb.work_totals, sizeof(wt_tot), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(&err_bits, lb.work + 1, sizeof(err_bits), hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
     float ms = 0.0f, kms = 0.0f;
     PE_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    if (graph && !rec) kms = ms;  // a replayed graph is timed as a whole
+    if (graph && !rec && !fixed) kms = ms;  // a replayed graph is timed as a whole
     else PE_HIP(hipEventElapsedTime(&kms, h->evk0, h->evk1));
     if (elapsed_ms) *elapsed_ms = ms;
     if (err_bits)
@@ -1228,6 +1311,51 @@ int perm_est_run(perm_est_t *h, int64_t n_traj, uint64_t seed, const perm_est_sc
                  void *stream) {
     return perm_est_run_range(h, 0, n_traj, seed, sched, res, logw, alive, path_hash, nullptr, nullptr,
                               stream);
+}
+
+int perm_est_run_range_noalloc(perm_est_t *h, int64_t first, int64_t count, uint64_t seed,
+                               const perm_est_schedule *sched, perm_est_result *res, double *logw,
+                               uint8_t *alive, uint64_t *path_hash, int32_t *path, int32_t *counters,
+                               void *stream) {
+    if (!h || !res) return fail(PE_EINVAL, "null handle or result");
+    if (h->mats.size() != 1) return fail(PE_EINVAL, "handle holds a batch: no-alloc runs take one matrix");
+    if (count < 1 || first < 0 || first + count > ((int64_t)1 << 32))
+        return fail(PE_EINVAL, "trajectory range must lie in [0, 2^32) and be non-empty");
+    int rc;
+    if ((rc = check_schedule(sched))) return rc;
+    PE_HIP(hipSetDevice(h->device));
+    char *base = nullptr;
+    if ((rc = noalloc_scratch(h->device, &base))) return rc;
+    // carve the scratch: launch bookkeeping, the outputs the caller left
+    // NULL, then per-wave state slots in what remains
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + off;
+        off = (off + bytes + 255) / 256 * 256;
+        return p;
+    };
+    LaunchBufs lb;
+    lb.work = reinterpret_cast<uint32_t *>(take(2 * sizeof(uint32_t)));
+    lb.work_totals = reinterpret_cast<unsigned long long *>(take(kWorkTotals * sizeof(unsigned long long)));
+    lb.args = reinterpret_cast<TrajArgs *>(take(sizeof(TrajArgs)));
+    lb.batch = reinterpret_cast<BatchArgs *>(take(sizeof(BatchArgs)));
+    lb.order = reinterpret_cast<int32_t *>(take(sizeof(int32_t)));
+    lb.item_off = reinterpret_cast<int64_t *>(take(2 * sizeof(int64_t)));
+    lb.seg = reinterpret_cast<ReduceSeg *>(take(sizeof(ReduceSeg)));
+    lb.stats = reinterpret_cast<DevStats *>(take(sizeof(DevStats)));
+    const size_t tmp_need = (logw ? 0 : 8 * (size_t)count + 256) + (alive ? 0 : (size_t)count + 256) +
+                            (counters ? 0 : 16 * (size_t)count + 256);
+    if (off + tmp_need > kScratchBytes)
+        return fail(PE_ENOTSUP, std::to_string(count) + " trajectories need more than the no-alloc scratch of " +
+                                    std::to_string(kScratchBytes) + " bytes for the outputs left NULL");
+    if (!logw) lb.tmp_logw = reinterpret_cast<double *>(take(8 * (size_t)count));
+    if (!alive) lb.tmp_alive = reinterpret_cast<uint8_t *>(take((size_t)count));
+    if (!counters) lb.tmp_counters = reinterpret_cast<int32_t *>(take(16 * (size_t)count));
+    lb.hbm_state = base + off;
+    lb.hbm_bytes = off < kScratchBytes ? kScratchBytes - off : 0;
+    std::vector<RunPart> parts(1);
+    parts[0] = RunPart{first, count, logw, alive, path_hash, path, counters};
+    return launch(h, sched, seed, parts, res, (hipStream_t)stream, 0, 0, nullptr, nullptr, false, &lb);
 }
 
 int perm_est_run_batch(perm_est_t *h, const int64_t *n_traj, uint64_t seed, const perm_est_schedule *sched,

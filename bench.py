@@ -45,7 +45,8 @@ METRIC = "effective samples/sec at equal relative error, learned vs plain, n=1e5
 HBM_PEAK_GBS = 8000.0
 
 KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/csrc/device.hpp",
-                  "paper_2608_15390_amd/csrc/mlp.hpp", "paper_2608_15390_amd/csrc/rows.hpp"]
+                  "paper_2608_15390_amd/csrc/mlp.hpp", "paper_2608_15390_amd/csrc/rows.hpp",
+                  "paper_2608_15390_amd/csrc/rows_learned.hpp"]
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # algorithmic FLOPs of one 16-candidate tile through the network (8 -> 64 -> 64 -> 1)
 FLOP_PER_TILE = 2 * 16 * (8 * 64 + 64 * 64 + 64)

@@ -20,6 +20,7 @@
 #include "prep.hpp"
 #include "reduce.hpp"
 #include "rows.hpp"
+#include "rows_learned.hpp"
 
 using namespace pe;
 
@@ -492,6 +493,17 @@ void launch_rows(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipSt
     else traj_rows_kernel<false><<<blocks, threads, shmem, s>>>(b);
 }
 
+// four-trajectories-per-wave kernel of the learned proposal
+const void *rows_learned_kernel_fn(bool wt) {
+    return wt ? (const void *)&traj_rows_learned_kernel<true> : (const void *)&traj_rows_learned_kernel<false>;
+}
+
+void launch_rows_learned(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+                         const BatchArgs *b) {
+    if (wt) traj_rows_learned_kernel<true><<<blocks, threads, shmem, s>>>(b);
+    else traj_rows_learned_kernel<false><<<blocks, threads, shmem, s>>>(b);
+}
+
 // upper bound on resident trajectory waves per CU for the default launch shape
 #ifndef PE_MAX_WAVES_PER_CU
 #define PE_MAX_WAVES_PER_CU 32
@@ -821,33 +833,49 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     B.mlp = learned ? h->mlp : nullptr;
     B.etab = learned ? h->etab : nullptr;
     // four trajectories per wave (16-lane rows) for a single large matrix
-    // under the plain estimator: short candidate lists leave most of a wave
-    // idle, so rows give 4x the parallelism per wave
+    // under the plain or the learned proposal: short candidate lists leave
+    // most of a wave idle, so rows give 4x the parallelism per wave
     const size_t block_fixed = learned ? (size_t)kMlpBlockBytes : 0;
     // (a wave of rows holds four trees; when even one such wave does not fit
     // a block's LDS, the matrix runs one trajectory per wave instead)
-    const bool rows = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD &&
-                      sched->sk_policy == PE_SK_NONE && hbm_cap > 0 && !parts[0].path &&
-                      !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY) &&
-                      block_fixed + 4 * tree_bytes + (size_t)lds_cap <= kLdsBlock;
+    const bool rows_ok = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD && hbm_cap > 0 &&
+                         !parts[0].path && !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY);
+    const bool rows_learned = rows_ok && learned && !gated &&
+                              block_fixed + 4 * tree_bytes + (size_t)kRowNetScratchBytes <= kLdsBlock;
+    const bool rows = rows_learned || (rows_ok && sched->sk_policy == PE_SK_NONE &&
+                                       block_fixed + 4 * tree_bytes + (size_t)lds_cap <= kLdsBlock);
+    const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt) : rows_kernel_fn(wt);
     const int tpw = rows ? 4 : 1;  // trajectories per wave
-    size_t per_wave = (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
+    size_t per_wave = rows_learned ? 4 * tree_bytes + (size_t)kRowNetScratchBytes
+                                   : (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
     int wpb = wpb_req > 0 ? wpb_req : 4;
     if (rows && wpb_req <= 0) {
-        // the row kernel's LDS (four trees per wave) limits residency: take the
-        // block size that keeps the most waves resident per CU
-        int best = 0;
-        for (int w : {4, 2, 1}) {
+        // the row kernels' LDS (four trees per wave) limits residency: take the
+        // block size that keeps the most of this launch's waves resident and
+        // spreads them over the most CUs (ties: the larger block)
+        const int64_t need = (total + tpw - 1) / tpw;
+        int64_t best_run = -1, best_cus = -1;
+        for (int w : {8, 4, 2, 1}) {
+            if (!rows_learned && w > 4) continue;
             const size_t sm = block_fixed + (size_t)w * per_wave;
             if (sm > kLdsBlock) continue;
             int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rows_kernel_fn(wt), w * kWave, sm) !=
-                    hipSuccess) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rows_fn, w * kWave, sm) != hipSuccess) {
                 (void)hipGetLastError();
                 continue;
             }
+            nb = std::min<int>(nb, (int)(kLdsCU / sm));
+            if (nb < 1) continue;
             const int resident = std::min(nb * w, PE_MAX_WAVES_PER_CU);
-            if (resident > best) { best = resident; wpb = w; }
+            const int64_t cap = (int64_t)resident * h->cu_count;
+            const int64_t run = std::min(need, cap);
+            const int64_t blocks_w = std::min<int64_t>((run + w - 1) / w, (int64_t)h->cu_count * nb);
+            const int64_t cus = std::min<int64_t>(blocks_w, h->cu_count);
+            if (run > best_run || (run == best_run && cus > best_cus)) {
+                best_run = run;
+                best_cus = cus;
+                wpb = w;
+            }
         }
     }
     wpb = (int)std::max<size_t>(1, std::min<size_t>(wpb, (kLdsBlock - block_fixed) / std::max<size_t>(per_wave, 1)));
@@ -859,7 +887,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     } else {
         // as many resident blocks as registers and LDS allow, up to the cap
         int nb = 0;
-        const void *kfn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sk_kind, dm, wt);
+        const void *kfn = rows ? rows_fn : traj_kernel_fn(sk_kind, dm, wt);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, wpb * kWave, shmem) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = std::max(1, 16 / wpb);
@@ -909,7 +937,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(lb.work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
         if (kernel_events) PE_HIP(hipEventRecord(h->evk0, q));
-        if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, lb.batch);
+        if (rows_learned) launch_rows_learned(wt, blocks, wpb * kWave, shmem, q, lb.batch);
+        else if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, lb.batch);
         else launch_traj(sk_kind, dm, wt, blocks, wpb * kWave, shmem, q, lb.batch);
         PE_HIP(hipGetLastError());
         if (kernel_events) PE_HIP(hipEventRecord(h->evk1, q));
@@ -919,7 +948,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         return PE_OK;
     };
     if (graph && !rec && !fixed) {
-        const void *fn = rows ? rows_kernel_fn(wt) : traj_kernel_fn(sk_kind, dm, wt);
+        const void *fn = rows ? rows_fn : traj_kernel_fn(sk_kind, dm, wt);
         const bool same = h->graph_exec && h->graph_fn == fn && h->graph_blocks == blocks &&
                           h->graph_threads == (unsigned)(wpb * kWave) && h->graph_shmem == shmem &&
                           h->graph_res == (res != nullptr);

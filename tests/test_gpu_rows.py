@@ -1,12 +1,14 @@
 """Four trajectories per wave (16-lane rows) for a single matrix in HBM
-scratch under the plain estimator (with or without the outer scaling):
-every trajectory equals the whole-wave kernel's and the oracle's, bit for
-bit, including lists longer than a row, weighted entries and dead ends."""
+scratch under the plain estimator (with or without the outer scaling) and
+under the learned proposal: every trajectory equals the whole-wave
+kernel's and the oracle's, bit for bit, including lists longer than a row,
+weighted entries and dead ends."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
+from oracle import mlp as R
 from oracle import oracle as O
 from paper_2608_15390_amd import inputs as G
 
@@ -30,13 +32,20 @@ CASES = [
 ]
 
 
+LEARNED = {"learned": 0.05, "learned_alpha0": 0.0, "learned_alpha1": 1.0}
+
+
 @pytest.mark.parametrize("case", [c[0] for c in CASES])
-@pytest.mark.parametrize("name", ["plain", "plain_outer"])
+@pytest.mark.parametrize("name", ["plain", "plain_outer", "learned", "learned_alpha0", "learned_alpha1"])
 def test_rows_match_whole_waves_and_oracle(case, name):
     import paper_2608_15390_amd as P
     M = dict(CASES)[case]()
+    model, alpha = None, 0.05
     if name == "plain_outer":
         sched = P.preset("plain", initial_dm=1, K0=100)
+    elif name in LEARNED:
+        sched = P.preset("learned")
+        model, alpha = R.quantize(R.init(61, scale=2.0)), LEARNED[name]
     else:
         sched = P.preset(name)
     count = 333
@@ -44,6 +53,8 @@ def test_rows_match_whole_waves_and_oracle(case, name):
     outs = []
     for wave_per_traj in (False, True):
         h = P.PermEst(M, force_hbm=True, wave_per_trajectory=wave_per_traj)
+        if model is not None:
+            h.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), alpha)
         outs.append(h.run(5, count, 17, sched, want_hash=True, want_counters=True))
         torch.cuda.synchronize()
         h.close()
@@ -54,7 +65,7 @@ def test_rows_match_whole_waves_and_oracle(case, name):
     for f in ("log_estimate", "p_match", "ess", "n_alive", "n_steps", "n_entries_scanned", "n_decrements"):
         a, b = rows["result"][f], whole["result"][f]
         assert a == b or (a != a and b != b), f
-    o = O.run(O.OMatrix(M), _osched(sched), seed=17, first=5, count=count, nthreads=8)
+    o = O.run(O.OMatrix(M), _osched(sched, model, alpha), seed=17, first=5, count=count, nthreads=8)
     al = rows["alive"].cpu().numpy()
     np.testing.assert_array_equal(al, o["alive"])
     np.testing.assert_array_equal(rows["path_hash"].cpu().numpy().view(np.uint64), o["path_hash"])

@@ -40,6 +40,18 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// gfx950's K = 32 tile: lane l holds A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+    typedef short s8 __attribute__((ext_vector_type(8)));
+    const s8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // Weights in matrix-core form, staged once per block in LDS, each lane's
 // four B-operand values contiguous (one 8-byte LDS read per MFMA):
 //   w1[nt][lane < 32][4] = W1[4 (lane / 16) + j][16 nt + lane % 16] (the K = 16
@@ -187,12 +199,23 @@ __device__ __forceinline__ float mlp_tile_logit_grid(const MlpLds *W, bf16x4 xb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) h1[nt][j] = (short)(__float_as_uint(act(acc[j])) >> 16);
     }
+    // layer 2 on K = 32 tiles. The contraction pairs A and B by slot, so
+    // slot (g, j) of block kk may stand for any layer-1 unit as long as both
+    // operands agree: slots j < 4 take unit 32 kk + 4 g + j (layer 1's tile
+    // 2 kk as this lane holds it), slots j >= 4 unit 32 kk + 16 + 4 g + j - 4
+    // (tile 2 kk + 1). Both operands are then concatenations of what the
+    // K = 16 layout already has in place. Every product and partial sum is
+    // exact on the grid, so the grouping does not change the logit.
     float part = 0.0f;
 #pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
         f32x4 acc = *reinterpret_cast<const f32x4 *>(&W->b2[16 * nt + g4]);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma16(load_b4(&W->w2[((ks * 4 + nt) * 64 + l) * 4]), h1[ks], acc);
+        for (int kk = 0; kk < 2; ++kk) {
+            const bf16x8 a = cat8(load_b4(&W->w2[((2 * kk * 4 + nt) * 64 + l) * 4]),
+                                  load_b4(&W->w2[(((2 * kk + 1) * 4 + nt) * 64 + l) * 4]));
+            acc = mfma32(a, cat8(h1[2 * kk], h1[2 * kk + 1]), acc);
+        }
         const f32x4 w3 = *reinterpret_cast<const f32x4 *>(&W->w3[16 * nt + g4]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) part = __builtin_fmaf(act(acc[j]), w3[j], part);

@@ -72,6 +72,7 @@ struct Prepared {
     int32_t *mate_r = nullptr, *mate_c = nullptr;  // perfect matching found by the initial filter
     uint16_t *deg0 = nullptr;
     uint32_t *tree0 = nullptr;
+    uint32_t *tree0a = nullptr;  // tree0 with level 1 packed as (degree << 8 | position)
     int32_t n_leaf = 0;
     TreeLayout tree{};
 
@@ -80,7 +81,7 @@ struct Prepared {
             dfree(row_ptr); dfree(col_idx); dfree(col_ptr); dfree(row_idx); dfree(csc2csr);
             dfree(val); dfree(val_csc); dfree(edge_row);
         }
-        dfree(r0); dfree(c0); dfree(deg0); dfree(tree0); dfree(mate_r); dfree(mate_c);
+        dfree(r0); dfree(c0); dfree(deg0); dfree(tree0); dfree(tree0a); dfree(mate_r); dfree(mate_c);
     }
 };
 
@@ -408,12 +409,17 @@ int build_prepared(MatData *h, int32_t initial_dm, int32_t K0, hipStream_t s, Pr
     for (int k = 0; k < T.levels; ++k) { T.off[k] = off; off += T.size[k]; }
     T.total = (off + 3) / 4 * 4;
     P.tree = T;
-    if ((rc = dalloc(&P.deg0, P.n_leaf)) || (rc = dalloc(&P.tree0, T.total))) return rc;
+    if ((rc = dalloc(&P.deg0, P.n_leaf)) || (rc = dalloc(&P.tree0, T.total)) || (rc = dalloc(&P.tree0a, T.total)))
+        return rc;
     k_deg_template<<<blocks_for(P.n_leaf), 256, 0, s>>>(n, P.n_leaf, P.row_ptr, P.col_ptr, P.deg0);
     k_tree_leaves<<<blocks_for(g1), 256, 0, s>>>(g1, P.deg0, P.tree0 + T.off[0]);
     for (int k = 1; k < T.levels; ++k)
         k_tree_up<<<blocks_for(T.size[k]), 256, 0, s>>>(T.size[k - 1], P.tree0 + T.off[k - 1], T.size[k],
                                                         P.tree0 + T.off[k]);
+    k_tree_leaves_argmin<<<blocks_for(g1), 256, 0, s>>>(g1, P.deg0, P.tree0a + T.off[0]);
+    if (T.levels > 1)
+        PE_HIP(hipMemcpyAsync(P.tree0a + T.off[1], P.tree0 + T.off[1], sizeof(uint32_t) * (T.total - T.off[1]),
+                              hipMemcpyDeviceToDevice, s));
     PE_HIP(hipGetLastError());
     PE_HIP(hipStreamSynchronize(s));
     return PE_OK;
@@ -741,6 +747,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.c0 = P->c0;
         a.deg0 = P->deg0;
         a.tree0 = P->tree0;
+        a.tree0a = P->tree0a;
         a.mate0_r = P->mate_r;
         a.mate0_c = P->mate_c;
         a.n_leaf = P->n_leaf;

@@ -344,6 +344,16 @@ __global__ void k_tree_leaves(int32_t groups, const uint16_t *deg0, uint32_t *lv
     lvl[g] = m;
 }
 
+// the same level with each node packed as (minimum << 8 | position of the
+// first leaf of that minimum within the group)
+__global__ void k_tree_leaves_argmin(int32_t groups, const uint16_t *deg0, uint32_t *lvl) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    uint32_t m = 0xFFFFFFFFu;
+    for (int32_t i = 0; i < 256; ++i) m = min(m, ((uint32_t)deg0[256 * g + i] << 8) | (uint32_t)i);
+    lvl[g] = m;
+}
+
 __global__ void k_tree_up(int32_t n_in, const uint32_t *in, int32_t n_out, uint32_t *out) {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_out) return;

@@ -120,6 +120,60 @@ __device__ __forceinline__ void row_candidate_stats(const RowTraj &T, bool ok, i
     }
 }
 
+// The row's min-tree with level 1 packed as (degree << 8 | position): each
+// level-1 node holds the minimum of its 256 leaves together with the
+// position of the first leaf of that degree, so selection names the vertex
+// from LDS alone; higher levels hold degrees.
+struct ArgTree {
+    const RowTraj &T;
+    __device__ uint32_t deg_at(int k, uint32_t val) const { return k == 0 ? val >> 8 : val; }
+    // a decrement of vertex y to degree nd
+    __device__ void lower(int32_t y, uint32_t nd) const {
+        atomicMin(T.level(0) + (y >> 8), (nd << 8) | (uint32_t)(y & 255));
+        if (T.a.tree.levels > 1) atomicMin(T.level(1) + (y >> 14), nd);
+        if (T.a.tree.levels > 2) atomicMin(T.level(2) + (y >> 20), nd);
+    }
+    // recompute the degree chain above level-1 node g
+    __device__ void refresh_upper(int32_t g) const {
+        const int rl = row_lane();
+        for (int k = 1; k < T.a.tree.levels; ++k) {
+            const int32_t h = g >> 6;
+            const int32_t base = 64 * h + 4 * rl;
+            uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (base + i < T.a.tree.size[k - 1]) {
+                    const uint32_t w = deg_at(k - 1, T.level(k - 1)[base + i]);
+                    m = w < m ? w : m;
+                }
+            m = row_min_u32(m);
+            if (rl == 0) T.level(k)[h] = m;
+            wave_fence();
+            g = h;
+        }
+    }
+};
+
+// (degree << 8 | position in the group) minimum over this lane's 16 leaves
+// (positions 16 rl .. 16 rl + 15 of group g), vertices skip_a, skip_b left out
+__device__ __forceinline__ uint32_t argmin16_skip(const uint4 &q0, const uint4 &q1, int32_t g, int32_t skip_a,
+                                                  int32_t skip_b) {
+    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    const int32_t p0 = 16 * row_lane();
+    uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int32_t pa = p0 + 2 * i, pb = pa + 1;
+        const int32_t xa = 256 * g + pa, xb = xa + 1;
+        const uint32_t lo = (xa == skip_a || xa == skip_b) ? 0xFFFFu : (w[i] & 0xFFFFu);
+        const uint32_t hi = (xb == skip_a || xb == skip_b) ? 0xFFFFu : (w[i] >> 16);
+        const uint32_t ca = (lo << 8) | (uint32_t)pa, cb = (hi << 8) | (uint32_t)pb;
+        m = ca < m ? ca : m;
+        m = cb < m ? cb : m;
+    }
+    return m;
+}
+
 // The learned proposal, four trajectories per wave; WT: weighted entries.
 template <bool WT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
@@ -145,6 +199,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     recast<int32_t>(state + L.lst_b),
                     reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes), n};
     const double alpha = a.mix_alpha;
+    const ArgTree AT{T};
     Work work;
     // per-row trajectory registers (uniform within the row)
     int phase = 0;  // 0 claim, 1 running, 2 no more work
@@ -178,7 +233,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
                 const auto dst = recast<uint4>(T.deg);
                 for (int32_t i = rl; i < a.n_leaf / 8; i += kRowLanes) dst[i] = src[i];
-                for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = gptr(a.tree0)[i];
+                for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = gptr(a.tree0a)[i];
                 wave_fence();
             }
         }
@@ -194,31 +249,60 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
             uint4 lq0 = make_uint4(0, 0, 0, 0), lq1 = lq0;  // this lane's 16 leaves of v's group
             uint32_t m_sel = 0;
             if (run) {
+                // the leftmost node of the minimum degree at each level is the
+                // row minimum of the code (lane, position) over the matches; at
+                // level 1 the code also carries the position of the vertex
                 const int top = a.tree.levels - 1;
-                const uint32_t m = T.global_min();
+                const int32_t tb = 4 * rl;
+                uint32_t w4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    w4[i] = tb + i < a.tree.size[top] ? AT.deg_at(top, T.level(top)[tb + i]) : 0xFFFFFFFFu;
+                const uint32_t m = row_min_u32(min(min(w4[0], w4[1]), min(w4[2], w4[3])));
                 m_sel = m;
                 int32_t g = 0;
-                for (int kk = top; kk >= 0 && g >= 0; --kk) {
-                    const int32_t base = 64 * g + 4 * rl;
-                    int j = 4;
+                uint32_t pos = 0;
+                if (top == 0) {
+                    uint32_t code = 0xFFFFFFFFu;
 #pragma unroll
                     for (int i = 3; i >= 0; --i)
-                        if (base + i < a.tree.size[kk] && T.level(kk)[base + i] == m) j = i;
-                    const uint32_t bits = row_bits(ballot(j < 4));
-                    const int src = __ffs(bits) - 1;
-                    const int js = row_read(j, src < 0 ? 0 : src);
-                    g = bits ? 64 * g + 4 * src + js : -1;
-                }
-                if (g >= 0) {
-                    T.load_leaves(g, lq0, lq1);
-                    const int j = first16(lq0, lq1, m);
-                    const uint32_t bits = row_bits(ballot(j < 16));
-                    const int src = __ffs(bits) - 1;
-                    const int js = row_read(j, src < 0 ? 0 : src);
-                    if (bits) {
-                        v = 256 * g + 16 * src + js;
-                        gsel = g;
+                        if (w4[i] == m) code = ((uint32_t)(tb + i) << 8) | (T.level(0)[tb + i] & 255u);
+                    const uint32_t cm = row_min_u32(code);
+                    g = (int32_t)(cm >> 8);
+                    pos = cm & 255u;
+                } else {
+                    uint32_t code = 0xFFFFFFFFu;
+#pragma unroll
+                    for (int i = 3; i >= 0; --i)
+                        if (w4[i] == m) code = (uint32_t)(tb + i);
+                    g = (int32_t)row_min_u32(code);
+                    for (int kk = top - 1; kk >= 0 && g >= 0; --kk) {
+                        const int32_t base = 64 * g + tb;
+                        code = 0xFFFFFFFFu;
+#pragma unroll
+                        for (int i = 3; i >= 0; --i) {
+                            if (base + i < a.tree.size[kk]) {
+                                const uint32_t val = T.level(kk)[base + i];
+                                if (AT.deg_at(kk, val) == m)
+                                    code = kk == 0 ? (((uint32_t)(tb + i) << 8) | (val & 255u)) : (uint32_t)(tb + i);
+                            }
+                        }
+                        const uint32_t cm = row_min_u32(code);
+                        if (cm == 0xFFFFFFFFu) {
+                            g = -1;
+                        } else if (kk == 0) {
+                            g = 64 * g + (int32_t)(cm >> 8);
+                            pos = cm & 255u;
+                        } else {
+                            g = 64 * g + (int32_t)cm;
+                        }
                     }
+                }
+                if (g >= 0 && g < a.tree.size[0]) {
+                    v = 256 * g + (int32_t)pos;
+                    gsel = g;
+                    // the group's leaves for its refresh after the step
+                    T.load_leaves(g, lq0, lq1);
                 }
             }
             bool dead = !run;
@@ -459,6 +543,13 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 }
                 h = splitmix_fold(h, ((uint64_t)(uint32_t)v << 32) | (uint32_t)u);
 
+                const int32_t gu = u >> 8;
+                // u's group needs a new minimum when u is its recorded argmin:
+                // read its leaves before this step's stores (stale values are
+                // only higher; the new degrees and u are patched in below)
+                const bool refresh_u = gu != gsel && T.level(0)[gu] == ((d_u << 8) | (uint32_t)(u & 255));
+                uint4 uq0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), uq1 = uq0;
+                if (refresh_u) T.load_leaves(gu, uq0, uq1);
                 // N_t(u) \ {v}: from the statistics' cache when u's list lies
                 // in its first 32 flattened entries, else read
                 int32_t ub, ue;
@@ -512,14 +603,6 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                         kb += __popc(msk);
                     }
                 }
-                const int32_t gu = u >> 8;
-                const uint32_t l1u_before = T.level(0)[gu];
-                // u's group needs a new minimum when u is it: read its leaves
-                // before this step's stores (stale values are only higher;
-                // the new degrees and u are patched in below)
-                const bool refresh_u = gu != gsel && d_u <= l1u_before;
-                uint4 uq0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), uq1 = uq0;
-                if (refresh_u) T.load_leaves(gu, uq0, uq1);
                 wave_fence();
                 // retire v and u, lower their other neighbours
                 if (rl == 0) {
@@ -531,9 +614,10 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     if (cand && cy != u) {
                         const uint32_t nd = cd - 1u;
                         T.deg[cy] = (uint16_t)nd;
-                        T.tree_lower(cy, nd);
-                        if ((cy >> 8) == gsel) dec_min_g = nd;
-                        if ((cy >> 8) == gu) dec_min_u = nd;
+                        AT.lower(cy, nd);
+                        const uint32_t pk = (nd << 8) | (uint32_t)(cy & 255);
+                        if ((cy >> 8) == gsel) dec_min_g = pk;
+                        if ((cy >> 8) == gu) dec_min_u = pk;
                     }
                 } else {
                     for (int32_t idx = rl; idx < kc; idx += kRowLanes) {
@@ -541,27 +625,30 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                         if (y == u) continue;
                         const uint32_t nd = (uint32_t)T.deg[y] - 1u;
                         T.deg[y] = (uint16_t)nd;
-                        T.tree_lower(y, nd);
-                        if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
-                        if ((y >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
+                        AT.lower(y, nd);
+                        const uint32_t pk = (nd << 8) | (uint32_t)(y & 255);
+                        if ((y >> 8) == gsel && pk < dec_min_g) dec_min_g = pk;
+                        if ((y >> 8) == gu && pk < dec_min_u) dec_min_u = pk;
                     }
                 }
                 if (fast_u) {
                     if (take) {
                         const uint32_t nd = bd - 1u;
                         T.deg[by] = (uint16_t)nd;
-                        T.tree_lower(by, nd);
-                        if ((by >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
-                        if ((by >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
+                        AT.lower(by, nd);
+                        const uint32_t pk = (nd << 8) | (uint32_t)(by & 255);
+                        if ((by >> 8) == gsel && pk < dec_min_g) dec_min_g = pk;
+                        if ((by >> 8) == gu && pk < dec_min_u) dec_min_u = pk;
                     }
                 } else {
                     for (int32_t idx = rl; idx < kb; idx += kRowLanes) {
                         const int32_t y = T.lst_b[idx];
                         const uint32_t nd = (uint32_t)T.deg[y] - 1u;
                         T.deg[y] = (uint16_t)nd;
-                        T.tree_lower(y, nd);
-                        if ((y >> 8) == gsel && nd < dec_min_g) dec_min_g = nd;
-                        if ((y >> 8) == gu && nd < dec_min_u) dec_min_u = nd;
+                        AT.lower(y, nd);
+                        const uint32_t pk = (nd << 8) | (uint32_t)(y & 255);
+                        if ((y >> 8) == gsel && pk < dec_min_g) dec_min_g = pk;
+                        if ((y >> 8) == gu && pk < dec_min_u) dec_min_u = pk;
                     }
                 }
                 if (rl == 0) {
@@ -572,19 +659,19 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 wave_fence();
                 // refresh v's group from the leaves read at selection time
                 {
-                    uint32_t mm = min16_skip(lq0, lq1, 256 * gsel + 16 * rl, v, u);
+                    uint32_t mm = argmin16_skip(lq0, lq1, gsel, v, u);
                     mm = row_min_u32(mm < dec_min_g ? mm : dec_min_g);
                     if (rl == 0) T.level(0)[gsel] = mm;
                     wave_fence();
                     // the upper levels hold every lowered value already
-                    if (mm > m_sel) T.refresh_upper(gsel);
+                    if ((mm >> 8) > m_sel) AT.refresh_upper(gsel);
                 }
                 if (refresh_u) {
-                    uint32_t mu = min16_skip(uq0, uq1, 256 * gu + 16 * rl, v, u);
+                    uint32_t mu = argmin16_skip(uq0, uq1, gu, v, u);
                     mu = row_min_u32(mu < dec_min_u ? mu : dec_min_u);
                     if (rl == 0) T.level(0)[gu] = mu;
                     wave_fence();
-                    if (mu > d_u) T.refresh_upper(gu);
+                    if ((mu >> 8) > d_u) AT.refresh_upper(gu);
                 }
                 steps = t + 1;
                 t += 1;

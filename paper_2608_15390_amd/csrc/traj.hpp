@@ -74,6 +74,7 @@ struct TrajArgs {
     const float *r0, *c0;      // shared outer scaling, nullptr = all ones
     const uint16_t *deg0;      // leaf template [n_leaf]
     const uint32_t *tree0;     // internal-node template [tree.total]
+    const uint32_t *tree0a;    // the same with level 1 as (degree << 8 | position)
     const int32_t *mate0_r;    // perfect matching of the filtered input, or nullptr
     const int32_t *mate0_c;
     int32_t n_leaf;

@@ -133,7 +133,10 @@ typedef struct {
     int64_t n_local_entries;   /* entries gathered or summed by local repair */
     int64_t n_local_values;    /* scaling values recomputed by local repair */
     int64_t n_mlp_tiles;       /* 16-candidate tiles through the learned
-                                  proposal's network                        */
+                                  proposal's network; where four
+                                  trajectories share a wave they share
+                                  tiles, so this count depends on the
+                                  launch shape (the results do not)         */
     int64_t n_entries_scanned_v; /* the part of n_entries_scanned read at the
                                     selected vertex v                      */
     double kernel_seconds;     /* device time of the trajectory kernel alone
@@ -390,6 +393,47 @@ int perm_est_mlp_train(perm_est_mlp_t *t, const float *x, const float *y, const 
                        double lr, uint64_t seed, double *loss_per_epoch, void *stream);
 
 void perm_est_mlp_destroy(perm_est_mlp_t *t);
+
+/* Multi-seed consensus diagnostics for a matrix whose permanent is not
+ * known (Sec. 4.4, "Real-world matrices with unknown permanents").  Host
+ * only; touches no device.
+ *   runs: host perm_est_result[n_variants][n_seeds] (variant-major), the
+ *         final statistics of each run (log_estimate, rse, n_traj, n_alive,
+ *         ess are read).
+ * With Y = exp(log_estimate), e = rse * Y the within-run standard error,
+ * per variant P: Ybar_P = mean over seeds, e_in = sqrt(sum e^2) / R,
+ * e_seed = sd(Y) / sqrt(R) (R - 1 denominator), e_P = max(e_in, e_seed);
+ * P_con = mean over variants of Ybar_P, e_con = sqrt(sum e_P^2) / V;
+ * D_max = max over pairs |Ybar_P - Ybar_P'| / sqrt(e_P^2 + e_P'^2) against
+ * c_Bonf = Phi^{-1}(1 - alpha / (2 C(V, 2))).  The checks of a provisional
+ * consensus are the PE_CON_* bits; the variant-wise 95 % t-interval is
+ * Ybar_P +- t_{0.975, R-1} e_P.
+ *   log_ybar, rel_e: host double[n_variants] (ln Ybar_P, e_P / Ybar_P), or
+ *         NULL.
+ * Errors: PE_EINVAL (n_variants < 2, n_seeds < 2, alpha outside (0, 1),
+ * NULL runs or out). */
+#define PE_CON_ALL_RUNS 1u     /* every run has n_traj > 0 and a log_estimate */
+#define PE_CON_T_INTERVALS 2u  /* the variant-wise t-intervals intersect     */
+#define PE_CON_BONFERRONI 4u   /* D_max <= c_Bonf                             */
+#define PE_CON_ALIVE 8u        /* every run has >= 1000 surviving trajectories */
+#define PE_CON_ESS 16u         /* every run has ESS >= 1000                   */
+#define PE_CON_HALF_WIDTH 32u  /* 1.96 e_con <= 0.1 P_con                     */
+#define PE_CON_ALL 63u
+typedef struct {
+    double log_p_con;      /* ln of the equal-variant consensus P_con        */
+    double log_e_con;      /* ln of its standard error e_con                 */
+    double rel_half_width; /* 1.96 e_con / P_con                             */
+    double variant_ratio;  /* largest variant mean / smallest                */
+    double min_ess;        /* smallest run ESS                               */
+    double d_max;
+    double c_bonf;
+    double t_crit;         /* t_{0.975, n_seeds - 1}                         */
+    uint32_t checks;       /* PE_CON_* bits that hold                        */
+    int32_t provisional;   /* 1 iff every check holds                        */
+} perm_est_consensus_result;
+
+int perm_est_consensus(int32_t n_variants, int32_t n_seeds, const perm_est_result *runs, double alpha,
+                       perm_est_consensus_result *out, double *log_ybar, double *rel_e);
 
 /* Release every device and host resource of the handle (NULL is a no-op). */
 void perm_est_destroy(perm_est_t *h);

@@ -21,7 +21,7 @@ from . import _native as N
 from .inputs import SparseMatrix
 
 __all__ = ["PermEst", "PermEstBatch", "ProposalNet", "preset", "Schedule", "PermEstError", "save_model",
-           "load_model"]
+           "load_model", "consensus"]
 
 PermEstError = N.PermEstError
 Schedule = N.Schedule
@@ -60,6 +60,36 @@ def load_model(path: str):
     a = C.c_double()
     N.check(N.load().perm_est_model_load(os.fsencode(path), p.ctypes.data, C.byref(a)))
     return p, a.value
+
+
+_CHECK_NAMES = {N.PE_CON_ALL_RUNS: "all_runs_present", N.PE_CON_T_INTERVALS: "t_intervals_intersect",
+                N.PE_CON_BONFERRONI: "d_max_within_bonferroni", N.PE_CON_ALIVE: "alive_at_least_1000",
+                N.PE_CON_ESS: "ess_at_least_1000", N.PE_CON_HALF_WIDTH: "half_width_within_10pct"}
+_RESULT_KEYS = ("log_estimate", "rse", "n_traj", "n_alive", "ess")
+
+
+def consensus(runs, alpha: float = 0.05) -> Dict:
+    """Multi-seed consensus diagnostics (perm_est_consensus) of runs given as
+    a list over variants of lists over seeds of result dicts (the `result`
+    of PermEst.run: log_estimate, rse, n_traj, n_alive, ess are used)."""
+    V, R = len(runs), len(runs[0])
+    if any(len(r) != R for r in runs):
+        raise ValueError("every variant needs the same number of seeds")
+    arr = (N.Result * (V * R))()
+    for p in range(V):
+        for r in range(R):
+            for k in _RESULT_KEYS:
+                setattr(arr[p * R + r], k, runs[p][r][k])
+    out = N.ConsensusResult()
+    ly = np.zeros(V)
+    re = np.zeros(V)
+    N.check(N.load().perm_est_consensus(V, R, arr, float(alpha), C.byref(out), ly.ctypes.data, re.ctypes.data))
+    d = out.as_dict()
+    d["checks"] = {name: bool(out.checks & bit) for bit, name in _CHECK_NAMES.items()}
+    d["provisional"] = bool(out.provisional)
+    d["log_ybar"] = ly.tolist()
+    d["rel_e"] = re.tolist()
+    return d
 
 
 def _ptr(t) -> Optional[int]:

@@ -65,6 +65,28 @@ class Result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ConsensusResult(C.Structure):
+    _fields_ = [
+        ("log_p_con", C.c_double),
+        ("log_e_con", C.c_double),
+        ("rel_half_width", C.c_double),
+        ("variant_ratio", C.c_double),
+        ("min_ess", C.c_double),
+        ("d_max", C.c_double),
+        ("c_bonf", C.c_double),
+        ("t_crit", C.c_double),
+        ("checks", C.c_uint32),
+        ("provisional", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+PE_CON_ALL_RUNS, PE_CON_T_INTERVALS, PE_CON_BONFERRONI = 1, 2, 4
+PE_CON_ALIVE, PE_CON_ESS, PE_CON_HALF_WIDTH = 8, 16, 32
+
+
 class RecordBuffers(C.Structure):
     _fields_ = [
         ("x", C.c_void_p),
@@ -96,6 +118,7 @@ EXPORTS = [
     "perm_est_mlp_loss_grad",
     "perm_est_mlp_train",
     "perm_est_mlp_destroy",
+    "perm_est_consensus",
     "perm_est_destroy",
     "perm_est_last_error",
 ]
@@ -158,6 +181,9 @@ def load():
     L.perm_est_mlp_train.restype = C.c_int
     L.perm_est_mlp_destroy.argtypes = [P]
     L.perm_est_mlp_destroy.restype = None
+    L.perm_est_consensus.argtypes = [C.c_int32, C.c_int32, C.POINTER(Result), C.c_double,
+                                     C.POINTER(ConsensusResult), P, P]
+    L.perm_est_consensus.restype = C.c_int
     L.perm_est_destroy.argtypes = [P]
     L.perm_est_destroy.restype = None
     L.perm_est_last_error.argtypes = []

@@ -9,7 +9,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = [os.path.join(PKG, "csrc", "perm_est.hip")]
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("device.hpp", "traj.hpp", "mlp.hpp", "rows.hpp", "rows_learned.hpp", "prep.hpp", "reduce.hpp")]
+HEADERS = [os.path.join(PKG, "csrc", f) for f in ("device.hpp", "traj.hpp", "mlp.hpp", "rows.hpp", "rows_learned.hpp", "prep.hpp", "reduce.hpp", "consensus.hpp")]
 LIB = os.path.join(PKG, "libpermest.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

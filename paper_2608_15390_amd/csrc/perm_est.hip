@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "perm_est.h"
+#include "consensus.hpp"
 #include "prep.hpp"
 #include "reduce.hpp"
 #include "rows.hpp"
@@ -1460,6 +1461,14 @@ uint64_t fnv1a64(const unsigned char *p, size_t n) {
     return h;
 }
 }  // namespace
+
+int perm_est_consensus(int32_t n_variants, int32_t n_seeds, const perm_est_result *runs, double alpha,
+                       perm_est_consensus_result *out, double *log_ybar, double *rel_e) {
+    if (!runs || !out) return fail(PE_EINVAL, "consensus: NULL runs or out");
+    if (n_variants < 2 || n_seeds < 2) return fail(PE_EINVAL, "consensus: needs at least 2 variants and 2 seeds");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(PE_EINVAL, "consensus: alpha must lie in (0, 1)");
+    return pe::consensus::run(n_variants, n_seeds, runs, alpha, out, log_ybar, rel_e);
+}
 
 int perm_est_model_save(const char *path, const float *params, double mix_alpha) {
     if (!path || !params) return fail(PE_EINVAL, "null path or params");

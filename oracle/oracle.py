@@ -60,6 +60,7 @@ class _Sched(C.Structure):
         ("local_gate", C.c_int32),
         ("model", C.c_void_p),
         ("mix_alpha", C.c_double),
+        ("local_cap", C.c_int32),
     ]
 
 
@@ -127,6 +128,7 @@ class Schedule:
     model: Optional[np.ndarray] = None   # quantised MLP parameters (float64, MLP_NPARAM)
     mix_alpha: float = 0.05
     local_gate: int = 0                  # learned only: gated local-repair fallback
+    local_cap: int = 0                   # local repair: 0 = exact, B > 0 = lists longer than B sampled
 
     def c(self) -> _Sched:
         if self.sk_policy == SK_LEARNED:
@@ -138,7 +140,7 @@ class Schedule:
             mp = None
         return _Sched(self.vertex_rule, self.sk_policy, self.dm_policy, self.initial_dm, self.K0,
                       self.K, self.theta_th, self.theta_tr, self.precision, self.local_gate, mp,
-                      self.mix_alpha)
+                      self.mix_alpha, self.local_cap)
 
     def replace(self, **kw) -> "Schedule":
         d = {k: v for k, v in self.__dict__.items() if not k.startswith("_")}

@@ -75,6 +75,9 @@ typedef struct {
     int32_t local_gate;  /* learned proposal: 1 = gated local-repair fallback */
     const double *model; /* learned proposal: quantised MLP parameters       */
     double mix_alpha;    /* uniform share mixed into the learned proposal    */
+    int32_t local_cap;   /* local repair: 0 = exact Eq. (local); B > 0 = a
+                            list longer than B entries is examined at B
+                            sampled positions only (bounded-work repair)  */
 } or_sched;
 
 enum { VR_MD = 0, VR_ROW = 1 };
@@ -593,6 +596,7 @@ typedef struct {
     uint8_t *mark_r, *mark_c;
     int32_t *list_r, *list_c;
     double *new_r, *new_c;
+    int32_t *pos_buf;  /* list positions examined by the local repair (n)  */
     uint64_t *heap;    /* binary min-heap of (degree << 32 | vertex) keys  */
     int64_t heap_n, heap_cap;
     dm_work dm;
@@ -681,7 +685,8 @@ static int tw_alloc(traj_work *w, const or_mat *A)
     w->list_c = malloc(sizeof(int32_t) * N);
     w->new_r = malloc(sizeof(double) * N);
     w->new_c = malloc(sizeof(double) * N);
-    if (!w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e || !w->cand_L ||
+    w->pos_buf = malloc(sizeof(int32_t) * N);
+    if (!w->pos_buf || !w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e || !w->cand_L ||
         !w->cand_w || !w->cand_s || !w->nb_v || !w->nb_u || !w->mark_r || !w->mark_c ||
         !w->list_r || !w->list_c || !w->new_r || !w->new_c)
         return -1;
@@ -693,7 +698,7 @@ static void tw_free(traj_work *w)
     free(w->act); free(w->deg); free(w->removed); free(w->r); free(w->c);
     free(w->cand_v); free(w->cand_e); free(w->cand_w); free(w->cand_s); free(w->cand_L);
     free(w->nb_v); free(w->nb_u); free(w->mark_r); free(w->mark_c);
-    free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c);
+    free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c); free(w->pos_buf);
     free(w->heap);
     dm_free(&w->dm);
 }
@@ -752,14 +757,53 @@ static void recount_degrees(const or_mat *A, traj_work *w)
         w->deg[x] = w->act[x] ? residual_neighbours(A, w, x, NULL, NULL) : 0;
 }
 
+/* Bounded-work local repair (the sampled variant that Sec. 3.3 suggests
+ * for hub vertices and leaves open).  With a cap B > 0, a vertex x whose
+ * list holds L_x > B entries is examined at B positions only:
+ *     p_k = (o_x + floor(k L_x / B)) mod L_x,  k = 0 .. B-1  (in k order),
+ * a systematic sample whose offset o_x = floor(R L_x / 2^32) takes R, the
+ * low 32 bits of the Philox draw (seed; trajectory, matrix, step t,
+ * draw 2^31 + x).  The active, non-removed entries among them are x's
+ * sampled child neighbourhood: it stands for N_{t+1}(x) when x's
+ * neighbours join R_loc or C_loc, and x's normalisation sum is estimated
+ * from it by the ratio d_x / a (d_x = x's residual degree in the child,
+ * a = the number of those entries):
+ *     new value of x = 1 / ((sum over them, in k order) * (d_x / a)),
+ * unchanged when a = 0 or the sum is 0.  Lists of at most B entries (and
+ * every list when B = 0) are used whole, as in Eq. (local).  Only the
+ * proposal changes, so the estimator stays unbiased (Sec. 3.1). */
+#define LOCAL_DRAW_BASE 0x80000000u
+
+static int32_t sample_positions(uint64_t seed, uint32_t k, uint32_t b, uint32_t t, int32_t x, int32_t L,
+                                int32_t cap, int32_t *pos)
+{
+    if (cap <= 0 || L <= cap) {
+        for (int32_t i = 0; i < L; ++i) pos[i] = i;
+        return L;
+    }
+    uint32_t R = (uint32_t)or_rng64(seed, k, b, t, LOCAL_DRAW_BASE | (uint32_t)x);
+    uint64_t o = ((uint64_t)R * (uint64_t)L) >> 32;
+    for (int32_t i = 0; i < cap; ++i)
+        pos[i] = (int32_t)((o + ((uint64_t)i * (uint64_t)L) / (uint64_t)cap) % (uint64_t)L);
+    return cap;
+}
+
+typedef struct {
+    uint64_t seed;
+    uint32_t k, b, t;
+    int32_t cap;
+} local_draw;
+
 /* Eq. (local): Jacobi repair of r on R_loc and c on C_loc, computed from
  * the pre-repair vectors and committed together. rho/gam are the removed
  * row/column, nb_rho = N_t(rho)\{gam} (columns), nb_gam = N_t(gam)\{rho}
- * (rows), given as vertex ids. */
+ * (rows), given as vertex ids.  ld->cap > 0 selects the bounded-work
+ * variant above. */
 static void local_repair(const or_mat *A, traj_work *w, int prec,
                          const int32_t *nb_rho, int32_t k_rho,
-                         const int32_t *nb_gam, int32_t k_gam)
+                         const int32_t *nb_gam, int32_t k_gam, const local_draw *ld)
 {
+    int32_t *pos = w->pos_buf;
     int32_t n = A->n, nr = 0, nc = 0;
     /* C_loc = N_t(rho)\{gam}  U  N_{t+1}(N_t(gam)\{rho}) */
     for (int32_t a = 0; a < k_rho; ++a) {
@@ -768,7 +812,10 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     }
     for (int32_t a = 0; a < k_gam; ++a) {
         int32_t i = nb_gam[a];
-        for (int32_t e = A->row_ptr[i]; e < A->row_ptr[i + 1]; ++e) {
+        int32_t b0 = A->row_ptr[i], L = A->row_ptr[i + 1] - b0;
+        int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, i, L, ld->cap, pos);
+        for (int32_t q = 0; q < np; ++q) {
+            int32_t e = b0 + pos[q];
             int32_t j = A->col_idx[e];
             if (!w->act[n + j] || w->removed[e]) continue;
             if (!w->mark_c[j]) { w->mark_c[j] = 1; w->list_c[nc++] = j; }
@@ -781,7 +828,10 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     }
     for (int32_t a = 0; a < k_rho; ++a) {
         int32_t j = nb_rho[a] - n;
-        for (int32_t p = A->col_ptr[j]; p < A->col_ptr[j + 1]; ++p) {
+        int32_t b0 = A->col_ptr[j], L = A->col_ptr[j + 1] - b0;
+        int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, n + j, L, ld->cap, pos);
+        for (int32_t q = 0; q < np; ++q) {
+            int32_t p = b0 + pos[q];
             int32_t i = A->row_idx[p], e = A->csc2csr[p];
             if (!w->act[i] || w->removed[e]) continue;
             if (!w->mark_r[i]) { w->mark_r[i] = 1; w->list_r[nr++] = i; }
@@ -791,7 +841,24 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     for (int32_t a = 0; a < nr; ++a) {
         int32_t i = w->list_r[a];
         double val = w->r[i];
-        if (prec == PREC_CONTRACT) {
+        int32_t b0 = A->row_ptr[i], L = A->row_ptr[i + 1] - b0;
+        if (ld->cap > 0 && L > ld->cap) {
+            /* sampled sum, ratio-scaled to the residual degree (binary32) */
+            int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, i, L, ld->cap, pos), cnt = 0;
+            float acc = 0.0f;
+            for (int32_t q = 0; q < np; ++q) {
+                int32_t e = b0 + pos[q];
+                int32_t j = A->col_idx[e];
+                if (!w->act[n + j] || w->removed[e]) continue;
+                float prod = entry_f(A, e) * (float)w->c[j];
+                acc = acc + prod;
+                ++cnt;
+            }
+            if (cnt > 0 && acc != 0.0f) {
+                float est = acc * ((float)w->deg[i] / (float)cnt);
+                val = (double)(1.0f / est);
+            }
+        } else if (prec == PREC_CONTRACT) {
             float acc = 0.0f;
             for (int32_t e = A->row_ptr[i]; e < A->row_ptr[i + 1]; ++e) {
                 int32_t j = A->col_idx[e];
@@ -814,7 +881,23 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     for (int32_t a = 0; a < nc; ++a) {
         int32_t j = w->list_c[a];
         double val = w->c[j];
-        if (prec == PREC_CONTRACT) {
+        int32_t b0 = A->col_ptr[j], L = A->col_ptr[j + 1] - b0;
+        if (ld->cap > 0 && L > ld->cap) {
+            int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, n + j, L, ld->cap, pos), cnt = 0;
+            float acc = 0.0f;
+            for (int32_t q = 0; q < np; ++q) {
+                int32_t p = b0 + pos[q];
+                int32_t i = A->row_idx[p], e = A->csc2csr[p];
+                if (!w->act[i] || w->removed[e]) continue;
+                float prod = entry_f(A, e) * (float)w->r[i];
+                acc = acc + prod;
+                ++cnt;
+            }
+            if (cnt > 0 && acc != 0.0f) {
+                float est = acc * ((float)w->deg[n + j] / (float)cnt);
+                val = (double)(1.0f / est);
+            }
+        } else if (prec == PREC_CONTRACT) {
             float acc = 0.0f;
             for (int32_t p = A->col_ptr[j]; p < A->col_ptr[j + 1]; ++p) {
                 int32_t i = A->row_idx[p], e = A->csc2csr[p];
@@ -1081,6 +1164,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         }
 
         /* ---- SK policy on the child */
+        const local_draw ld = {seed, k, b, (uint32_t)t, S->local_cap};
         int nit = 0;
         if (S->sk_policy == SK_FIXED) nit = S->K;
         else if (S->sk_policy == SK_ADAPTIVE) {
@@ -1096,13 +1180,13 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
             out->n_sk_sweeps += nit;
             if (events) events[2 * t + 1] = nit;
         } else if (S->sk_policy == SK_LOCAL) {
-            local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam);
+            local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam, &ld);
             out->n_local += 1;
             if (events) events[2 * t + 1] = 1;
         } else if (gate) {
             fb = z < S->theta_th || run_dm;
             if (fb) {
-                local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam);
+                local_repair(A, w, prec, w->nb_v, k_rho, w->nb_u, k_gam, &ld);
                 out->n_local += 1;
                 if (events) events[2 * t + 1] = 1;
             }

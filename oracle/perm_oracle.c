@@ -197,6 +197,37 @@ double or_ryser_f64(int32_t n, const double *dense)
     return (double)total;
 }
 
+/* Permanent of a dense nonnegative matrix (n <= 26) by the row-by-row
+ * expansion over column subsets: f(S) is the permanent of the first |S|
+ * rows restricted to the columns in S, f(empty) = 1 and
+ *     f(S) = sum over j in S of a[|S| - 1][j] * f(S without j),
+ * so per(A) = f(all columns).  Every term is nonnegative, so the binary64
+ * result carries no cancellation (relative error about 2n ulps), unlike
+ * Ryser's alternating sum.  Needs 2^n doubles of workspace; returns -1.0
+ * when that cannot be allocated. */
+double or_perm_subset_dp(int32_t n, const double *dense)
+{
+    if (n == 0) return 1.0;
+    if (n > 26) return -1.0;
+    size_t N = (size_t)1 << n;
+    double *f = malloc(sizeof(double) * N);
+    if (!f) return -1.0;
+    f[0] = 1.0;
+    for (size_t S = 1; S < N; ++S) {
+        int i = __builtin_popcountll((unsigned long long)S) - 1;   /* the row added last */
+        const double *row = dense + (size_t)i * (size_t)n;
+        double acc = 0.0;
+        for (size_t R = S; R; R &= R - 1) {
+            int j = __builtin_ctzll((unsigned long long)R);
+            if (row[j] != 0.0) acc += row[j] * f[S & ~((size_t)1 << j)];
+        }
+        f[S] = acc;
+    }
+    double out = f[N - 1];
+    free(f);
+    return out;
+}
+
 /* ---------------------------------------------------------- matrix setup */
 /* csc2csr[p] = CSR position of the entry at CSC position p. */
 int or_mat_init(or_mat *A, int32_t *csc2csr_out)
@@ -597,6 +628,7 @@ typedef struct {
     int32_t *list_r, *list_c;
     double *new_r, *new_c;
     int32_t *pos_buf;  /* list positions examined by the local repair (n)  */
+    int32_t *kept_buf; /* a list as the trajectories start it (n)          */
     uint64_t *heap;    /* binary min-heap of (degree << 32 | vertex) keys  */
     int64_t heap_n, heap_cap;
     dm_work dm;
@@ -686,7 +718,8 @@ static int tw_alloc(traj_work *w, const or_mat *A)
     w->new_r = malloc(sizeof(double) * N);
     w->new_c = malloc(sizeof(double) * N);
     w->pos_buf = malloc(sizeof(int32_t) * N);
-    if (!w->pos_buf || !w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e || !w->cand_L ||
+    w->kept_buf = malloc(sizeof(int32_t) * N);
+    if (!w->pos_buf || !w->kept_buf || !w->act || !w->deg || !w->removed || !w->r || !w->c || !w->cand_v || !w->cand_e || !w->cand_L ||
         !w->cand_w || !w->cand_s || !w->nb_v || !w->nb_u || !w->mark_r || !w->mark_c ||
         !w->list_r || !w->list_c || !w->new_r || !w->new_c)
         return -1;
@@ -698,7 +731,7 @@ static void tw_free(traj_work *w)
     free(w->act); free(w->deg); free(w->removed); free(w->r); free(w->c);
     free(w->cand_v); free(w->cand_e); free(w->cand_w); free(w->cand_s); free(w->cand_L);
     free(w->nb_v); free(w->nb_u); free(w->mark_r); free(w->mark_c);
-    free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c); free(w->pos_buf);
+    free(w->list_r); free(w->list_c); free(w->new_r); free(w->new_c); free(w->pos_buf); free(w->kept_buf);
     free(w->heap);
     dm_free(&w->dm);
 }
@@ -758,8 +791,10 @@ static void recount_degrees(const or_mat *A, traj_work *w)
 }
 
 /* Bounded-work local repair (the sampled variant that Sec. 3.3 suggests
- * for hub vertices and leaves open).  With a cap B > 0, a vertex x whose
- * list holds L_x > B entries is examined at B positions only:
+ * for hub vertices and leaves open).  The list of a vertex x here is the
+ * list trajectories start from: x's entries that the shared initial
+ * filter kept, in list order.  With a cap B > 0, a vertex whose list holds
+ * L_x > B entries is examined at B of them only, the ones at list indices
  *     p_k = (o_x + floor(k L_x / B)) mod L_x,  k = 0 .. B-1  (in k order),
  * a systematic sample whose offset o_x = floor(R L_x / 2^32) takes R, the
  * low 32 bits of the Philox draw (seed; trajectory, matrix, step t,
@@ -774,25 +809,46 @@ static void recount_degrees(const or_mat *A, traj_work *w)
  * proposal changes, so the estimator stays unbiased (Sec. 3.1). */
 #define LOCAL_DRAW_BASE 0x80000000u
 
-static int32_t sample_positions(uint64_t seed, uint32_t k, uint32_t b, uint32_t t, int32_t x, int32_t L,
-                                int32_t cap, int32_t *pos)
-{
-    if (cap <= 0 || L <= cap) {
-        for (int32_t i = 0; i < L; ++i) pos[i] = i;
-        return L;
-    }
-    uint32_t R = (uint32_t)or_rng64(seed, k, b, t, LOCAL_DRAW_BASE | (uint32_t)x);
-    uint64_t o = ((uint64_t)R * (uint64_t)L) >> 32;
-    for (int32_t i = 0; i < cap; ++i)
-        pos[i] = (int32_t)((o + ((uint64_t)i * (uint64_t)L) / (uint64_t)cap) % (uint64_t)L);
-    return cap;
-}
-
 typedef struct {
     uint64_t seed;
     uint32_t k, b, t;
     int32_t cap;
+    const uint8_t *removed0;  /* entries the shared initial filter removed */
 } local_draw;
+
+/* x's list as the trajectories start it: absolute CSR (row x) or CSC
+ * (column x) positions of the entries the initial filter kept. */
+static int32_t start_list(const or_mat *A, const uint8_t *removed0, int32_t x, int32_t *out)
+{
+    int32_t n = A->n, L = 0;
+    if (x < n) {
+        for (int32_t e = A->row_ptr[x]; e < A->row_ptr[x + 1]; ++e)
+            if (!removed0[e]) out[L++] = e;
+    } else {
+        for (int32_t p = A->col_ptr[x - n]; p < A->col_ptr[x - n + 1]; ++p)
+            if (!removed0[A->csc2csr[p]]) out[L++] = p;
+    }
+    return L;
+}
+
+/* The positions of x's list that the repair examines, in examination
+ * order; *sampled tells whether the list was longer than the cap. */
+static int32_t examined_positions(const or_mat *A, const local_draw *ld, int32_t x, int32_t *kept,
+                                  int32_t *pos, int *sampled)
+{
+    int32_t L = start_list(A, ld->removed0, x, kept);
+    if (ld->cap <= 0 || L <= ld->cap) {
+        for (int32_t i = 0; i < L; ++i) pos[i] = kept[i];
+        *sampled = 0;
+        return L;
+    }
+    uint32_t R = (uint32_t)or_rng64(ld->seed, ld->k, ld->b, ld->t, LOCAL_DRAW_BASE | (uint32_t)x);
+    uint64_t o = ((uint64_t)R * (uint64_t)L) >> 32;
+    for (int32_t i = 0; i < ld->cap; ++i)
+        pos[i] = kept[(o + ((uint64_t)i * (uint64_t)L) / (uint64_t)ld->cap) % (uint64_t)L];
+    *sampled = 1;
+    return ld->cap;
+}
 
 /* Eq. (local): Jacobi repair of r on R_loc and c on C_loc, computed from
  * the pre-repair vectors and committed together. rho/gam are the removed
@@ -803,8 +859,9 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
                          const int32_t *nb_rho, int32_t k_rho,
                          const int32_t *nb_gam, int32_t k_gam, const local_draw *ld)
 {
-    int32_t *pos = w->pos_buf;
+    int32_t *pos = w->pos_buf, *kept = w->kept_buf;
     int32_t n = A->n, nr = 0, nc = 0;
+    int smp;
     /* C_loc = N_t(rho)\{gam}  U  N_{t+1}(N_t(gam)\{rho}) */
     for (int32_t a = 0; a < k_rho; ++a) {
         int32_t j = nb_rho[a] - n;
@@ -812,10 +869,9 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     }
     for (int32_t a = 0; a < k_gam; ++a) {
         int32_t i = nb_gam[a];
-        int32_t b0 = A->row_ptr[i], L = A->row_ptr[i + 1] - b0;
-        int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, i, L, ld->cap, pos);
+        int32_t np = examined_positions(A, ld, i, kept, pos, &smp);
         for (int32_t q = 0; q < np; ++q) {
-            int32_t e = b0 + pos[q];
+            int32_t e = pos[q];
             int32_t j = A->col_idx[e];
             if (!w->act[n + j] || w->removed[e]) continue;
             if (!w->mark_c[j]) { w->mark_c[j] = 1; w->list_c[nc++] = j; }
@@ -828,10 +884,9 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     }
     for (int32_t a = 0; a < k_rho; ++a) {
         int32_t j = nb_rho[a] - n;
-        int32_t b0 = A->col_ptr[j], L = A->col_ptr[j + 1] - b0;
-        int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, n + j, L, ld->cap, pos);
+        int32_t np = examined_positions(A, ld, n + j, kept, pos, &smp);
         for (int32_t q = 0; q < np; ++q) {
-            int32_t p = b0 + pos[q];
+            int32_t p = pos[q];
             int32_t i = A->row_idx[p], e = A->csc2csr[p];
             if (!w->act[i] || w->removed[e]) continue;
             if (!w->mark_r[i]) { w->mark_r[i] = 1; w->list_r[nr++] = i; }
@@ -841,13 +896,13 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     for (int32_t a = 0; a < nr; ++a) {
         int32_t i = w->list_r[a];
         double val = w->r[i];
-        int32_t b0 = A->row_ptr[i], L = A->row_ptr[i + 1] - b0;
-        if (ld->cap > 0 && L > ld->cap) {
+        int32_t np = examined_positions(A, ld, i, kept, pos, &smp);
+        if (smp) {
             /* sampled sum, ratio-scaled to the residual degree (binary32) */
-            int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, i, L, ld->cap, pos), cnt = 0;
+            int32_t cnt = 0;
             float acc = 0.0f;
             for (int32_t q = 0; q < np; ++q) {
-                int32_t e = b0 + pos[q];
+                int32_t e = pos[q];
                 int32_t j = A->col_idx[e];
                 if (!w->act[n + j] || w->removed[e]) continue;
                 float prod = entry_f(A, e) * (float)w->c[j];
@@ -881,12 +936,12 @@ static void local_repair(const or_mat *A, traj_work *w, int prec,
     for (int32_t a = 0; a < nc; ++a) {
         int32_t j = w->list_c[a];
         double val = w->c[j];
-        int32_t b0 = A->col_ptr[j], L = A->col_ptr[j + 1] - b0;
-        if (ld->cap > 0 && L > ld->cap) {
-            int32_t np = sample_positions(ld->seed, ld->k, ld->b, ld->t, n + j, L, ld->cap, pos), cnt = 0;
+        int32_t np = examined_positions(A, ld, n + j, kept, pos, &smp);
+        if (smp) {
+            int32_t cnt = 0;
             float acc = 0.0f;
             for (int32_t q = 0; q < np; ++q) {
-                int32_t p = b0 + pos[q];
+                int32_t p = pos[q];
                 int32_t i = A->row_idx[p], e = A->csc2csr[p];
                 if (!w->act[i] || w->removed[e]) continue;
                 float prod = entry_f(A, e) * (float)w->r[i];
@@ -1164,7 +1219,7 @@ static void run_traj(const or_mat *A, const or_sched *S, const uint8_t *removed0
         }
 
         /* ---- SK policy on the child */
-        const local_draw ld = {seed, k, b, (uint32_t)t, S->local_cap};
+        const local_draw ld = {seed, k, b, (uint32_t)t, S->local_cap, removed0};
         int nit = 0;
         if (S->sk_policy == SK_FIXED) nit = S->K;
         else if (S->sk_policy == SK_ADAPTIVE) {

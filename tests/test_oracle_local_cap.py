@@ -76,10 +76,20 @@ def _positions(seed, k, t, x, L, cap):
 def test_sampled_repair_follows_its_definition(dm, cap):
     sched = O.Schedule(sk_policy=O.SK_LOCAL, dm_policy=dm, initial_dm=1, K0=5, theta_th=0.5, local_cap=cap)
     g = np.random.default_rng(77 + cap)
-    checked = sampled = 0
+    checked = sampled = filtered = 0
     f32 = np.float32
-    for trial in range(6):
-        M = G.planted_bernoulli(14, 0.35, int(g.integers(1 << 30)), planted="random")
+    for trial in range(8):
+        if trial >= 6:
+            # block upper-triangular: the off-diagonal block lies in no perfect
+            # matching, so the initial filter removes it from every list
+            h = np.random.default_rng(trial)
+            blk = (h.random((14, 14)) < 0.45) | np.eye(14, dtype=bool)
+            blk[7:, :7] = False
+            r, c = np.nonzero(blk)
+            perm_r, perm_c = h.permutation(14), h.permutation(14)
+            M = G.from_coo(14, perm_r[r], perm_c[c])
+        else:
+            M = G.planted_bernoulli(14, 0.35, int(g.integers(1 << 30)), planted="random")
         if trial % 2:
             M = G.with_weights(M, trial)
         A = O.OMatrix(M)
@@ -88,6 +98,14 @@ def test_sampled_repair_follows_its_definition(dm, cap):
         D = dense_values(M).astype(np.float32)
         full = O.probe(A, sched, pre, seed=5, k=trial, forced=[], stop_at=-1)
         path = full["path"].reshape(-1, 2)
+        # the lists trajectories start from: entries the initial filter kept,
+        # in list order (rows by column, columns by row)
+        kept = pre.removed[: M.nnz] == 0
+        filtered += int((~kept).sum())
+        row_lists = [[int(M.col_idx[e]) for e in range(M.row_ptr[i], M.row_ptr[i + 1]) if kept[e]]
+                     for i in range(n)]
+        col_lists = [[i for i in range(n) for e in range(M.row_ptr[i], M.row_ptr[i + 1])
+                      if kept[e] and M.col_idx[e] == j] for j in range(n)]
         for t in range(min(full["steps"], n - 1)):
             bef = O.probe(A, sched, pre, seed=5, k=trial, forced=path[:t, 1].tolist(), stop_at=t)
             aft = O.probe(A, sched, pre, seed=5, k=trial, forced=path[:t + 1, 1].tolist(), stop_at=t + 1)
@@ -99,14 +117,14 @@ def test_sampled_repair_follows_its_definition(dm, cap):
             Bn = residual_adjacency(M, aft["act"], aft["removed"])
 
             def row_sample(i):   # sampled child neighbours (columns) of row i, in sample order
-                lo = M.row_ptr[i]
-                pos = _positions(5, trial, t, i, M.row_ptr[i + 1] - lo, cap)
-                return [int(M.col_idx[lo + p]) for p in pos if Bn[i, M.col_idx[lo + p]]]
+                cols = row_lists[i]
+                pos = _positions(5, trial, t, i, len(cols), cap)
+                return [cols[p] for p in pos if Bn[i, cols[p]]]
 
             def col_sample(j):   # sampled child neighbours (rows) of column j
-                lo = M.col_ptr[j]
-                pos = _positions(5, trial, t, n + j, M.col_ptr[j + 1] - lo, cap)
-                return [int(M.row_idx[lo + p]) for p in pos if Bn[M.row_idx[lo + p], j]]
+                rows = col_lists[j]
+                pos = _positions(5, trial, t, n + j, len(rows), cap)
+                return [rows[p] for p in pos if Bn[rows[p], j]]
 
             Nr = set(np.nonzero(Bt[rho])[0]) - {gam}
             Ng = set(np.nonzero(Bt[:, gam])[0]) - {rho}
@@ -117,7 +135,7 @@ def test_sampled_repair_follows_its_definition(dm, cap):
                 if i not in R_loc:
                     assert aft["r"][i] == bef["r"][i]
                     continue
-                L = M.row_ptr[i + 1] - M.row_ptr[i]
+                L = len(row_lists[i])
                 if L <= cap:
                     s = (D[i] * Bn[i] * c0).astype(np.float64).sum()
                     if s > 0:
@@ -136,7 +154,7 @@ def test_sampled_repair_follows_its_definition(dm, cap):
                 if j not in C_loc:
                     assert aft["c"][j] == bef["c"][j]
                     continue
-                L = M.col_ptr[j + 1] - M.col_ptr[j]
+                L = len(col_lists[j])
                 if L <= cap:
                     s = (D[:, j] * Bn[:, j] * r0).astype(np.float64).sum()
                     if s > 0:
@@ -152,4 +170,4 @@ def test_sampled_repair_follows_its_definition(dm, cap):
                 assert aft["c"][j] == want
                 sampled += 1
             checked += 1
-    assert checked > 20 and sampled > 50
+    assert checked > 20 and sampled > 50 and filtered > 10

@@ -84,6 +84,8 @@ def lib():
         L.or_ryser_u01.argtypes = [C.c_int32, P, P]
         L.or_ryser_f64.argtypes = [C.c_int32, P]
         L.or_ryser_f64.restype = C.c_double
+        L.or_perm_subset_dp.argtypes = [C.c_int32, P]
+        L.or_perm_subset_dp.restype = C.c_double
         L.or_mat_init.argtypes = [P, P]
         L.or_mat_init.restype = C.c_int
         L.or_support_filter.argtypes = [P, P, P]
@@ -331,6 +333,21 @@ def ryser_f64(dense) -> float:
     if n == 0:
         return 1.0
     return float(lib().or_ryser_f64(n, _p(A)))
+
+
+def perm_subset_dp(dense) -> float:
+    """Permanent of a dense nonnegative matrix (n <= 26) by the subset
+    expansion (no cancellation; FP64)."""
+    A = np.ascontiguousarray(dense, dtype=np.float64)
+    n = A.shape[0]
+    if n > 26:
+        raise ValueError("n too large for the subset expansion")
+    if (A < 0).any():
+        raise ValueError("the subset expansion is for nonnegative matrices")
+    v = float(lib().or_perm_subset_dp(n, _p(A)))
+    if v < 0:
+        raise MemoryError("workspace of 2^n doubles")
+    return v
 
 
 def plog2(s: float) -> float:

@@ -350,6 +350,28 @@ def config_band(seed: int = 1, n: int = 100_000):
     return banded(n, 4, 0.5, seed, outer_only=True)
 
 
+BLOCK_ORDERS = (100, 250, 500, 1000, 2000)
+BLOCK_DELETION = (0.1, 0.3, 0.5, 0.7, 0.9)
+
+
+def block_set_seed(i_order: int, i_p: int, weighted: bool) -> int:
+    """Generator seed of one matrix of the hidden-block study set."""
+    return 5000 + 100 * i_order + 10 * i_p + (1 if weighted else 0)
+
+
+def config_blocks(orders: Sequence[int] = BLOCK_ORDERS, deletion: Sequence[float] = BLOCK_DELETION):
+    """The hidden-block study set (Sec. 4, "Matrices used"): for every order
+    n in {100, 250, 500, 1000, 2000} and deletion probability p in {0.1, 0.3,
+    0.5, 0.7, 0.9} one binary and one weighted (entries U[1, 1.5], support
+    drawn independently) randomly permuted block-diagonal matrix with
+    blocks of order 20 or 25: 50 matrices.  Yields (name, matrix, blocks)."""
+    for i, n in enumerate(orders):
+        for j, p in enumerate(deletion):
+            for w in (False, True):
+                M, blocks = hidden_block_diagonal(n, p, block_set_seed(BLOCK_ORDERS.index(n), j, w), weighted=w)
+                yield f"n{n}_p{p:g}_{'w' if w else 'b'}", M, blocks
+
+
 def with_weights(M: SparseMatrix, seed: int, lo: float = 1.0, hi: float = 1.5) -> SparseMatrix:
     """Same pattern with entry values uniform in [lo, hi] (float32)."""
     g = _rng(seed, 8)

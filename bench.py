@@ -17,6 +17,8 @@ sum X^2 pooled over all M trajectories (log-sum-exp over the per-step
 ln X) and T the wall time of the K timed steps.  The plain scaled method
 (one local SK repair per step, no inner filter) then runs the same ids in
 the same chunks, timed the same way, and the ratio of the two is reported.
+Launches run up to --streams at a time (one handle and HIP stream each,
+default 4), so that 5000-trajectory launches still fill the chip.
 At n = 1e5 both ESS values collapse towards 1 (see "degenerate"), so the
 same comparison also runs at n = 1e3 and 1e4 over five run seeds (mean
 ratio, bootstrap interval, time to RSE 0.1 and 0.01), and on band matrices
@@ -48,6 +50,10 @@ KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/cs
                   "paper_2608_15390_amd/csrc/mlp.hpp", "paper_2608_15390_amd/csrc/rows.hpp",
                   "paper_2608_15390_amd/csrc/rows_learned.hpp"]
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# the dominant kernel of each timed method on the large workload (one
+# matrix of n = 1e5: four trajectories per wave for the network-only
+# learned proposal, one per wave for the local repair)
+KERNEL_NAME = {"learned": "pe::traj_rows_learned_kernel<false>", "plain": "pe::traj_kernel<3, false, false>"}
 # algorithmic FLOPs of one 16-candidate tile through the network (8 -> 64 -> 64 -> 1)
 FLOP_PER_TILE = 2 * 16 * (8 * 64 + 64 * 64 + 64)
 
@@ -141,29 +147,69 @@ def pooled(lw: np.ndarray, al: np.ndarray, secs: float, steps: int = 0) -> dict:
     return r
 
 
-def chunked_run(est, ranges, seed, sched, label):
-    """The trajectory ids of `ranges` [(first, count), ...] as consecutive
-    launches (results are identical per id), each bracketed by device
-    synchronisation; returns the pooled statistics, the wall time summed
-    over the launches, and the per-launch results."""
+def run_concurrent(ests, ranges, seed, sched, streams, label, want=True):
+    """The launches of `ranges` [(first, count), ...] spread round-robin over
+    the handles `ests` (one per stream), each handle driven by its own host
+    thread on its own HIP stream, so that up to len(ests) launches are in
+    flight together (a library call blocks only its own thread; results are
+    identical per id whatever the grouping).  Returns the per-launch outputs
+    in range order."""
+    import threading
+
     import torch
 
-    lws, als, secs, steps, per_launch = [], [], 0.0, 0, []
-    done, total = 0, sum(c for _, c in ranges)
-    for first, c in ranges:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = est.run(first, c, seed, sched, want_logw=True, want_alive=True)
-        torch.cuda.synchronize()
-        secs += time.perf_counter() - t0
-        lws.append(out["logw"].cpu().numpy())
-        als.append(out["alive"].cpu().numpy())
-        steps += out["result"]["n_steps"]
-        per_launch.append(out["result"])
-        done += c
-        print(f"[bench]   {label}: {done}/{total} trajectories, {secs:.1f} s", file=sys.stderr, flush=True)
-    r = pooled(np.concatenate(lws), np.concatenate(als).astype(bool), secs, steps)
-    return r, secs, per_launch
+    outs = [None] * len(ranges)
+    errs = []
+    done = [0]
+    lock = threading.Lock()
+
+    def worker(j):
+        try:
+            with torch.cuda.stream(streams[j]):
+                for i in range(j, len(ranges), len(ests)):
+                    first, cnt = ranges[i]
+                    outs[i] = ests[j].run(first, cnt, seed, sched, want_logw=want, want_alive=want,
+                                          stream=streams[j])
+                    with lock:
+                        done[0] += 1
+                        if label:
+                            print(f"[bench]   {label}: launch {done[0]}/{len(ranges)} done", file=sys.stderr,
+                                  flush=True)
+        except BaseException as e:  # re-raised in the caller
+            errs.append(e)
+
+    threads = [threading.Thread(target=worker, args=(j,)) for j in range(min(len(ests), len(ranges)))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errs:
+        raise errs[0]
+    return outs
+
+
+def timed_concurrent(ests, ranges, seed, sched, streams, label):
+    """run_concurrent bracketed by device synchronisation; the pooled
+    statistics, the wall time and the per-launch results."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = run_concurrent(ests, ranges, seed, sched, streams, label)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    lw = np.concatenate([o["logw"].cpu().numpy() for o in outs])
+    al = np.concatenate([o["alive"].cpu().numpy() for o in outs]).astype(bool)
+    results = [o["result"] for o in outs]
+    return pooled(lw, al, secs, sum(r["n_steps"] for r in results)), secs, results, lw, al
+
+
+def launch_shape(r):
+    """The launch shape a run used, from its result record."""
+    return {"blocks": r["launch_blocks"], "waves_per_block": r["launch_waves_per_block"],
+            "trajectories_per_wave": r["launch_trajectories_per_wave"],
+            "blocks_per_cu": r["launch_blocks_per_cu"],
+            "waves_per_cu": r["launch_blocks_per_cu"] * r["launch_waves_per_block"]}
 
 
 def summary(r, secs):
@@ -316,13 +362,28 @@ def batch_main(args) -> int:
 
     import paper_2608_15390_amd as P
     from paper_2608_15390_amd import inputs as G
+    from paper_2608_15390_amd import learned as LR
 
-    mats = G.config_batch(1)
-    n_traj = args.n_traj or 4096
-    sched = P.preset(args.batch_schedule)
+    stress = args.workload == "stress"
+    if stress:
+        # 64 power-law matrices, n log-uniform in [1e4, 1e6], learned proposal
+        mats = G.config_stress(1)
+        sched_name = args.batch_schedule if args.batch_schedule != "adaptive_threshold" else "learned"
+        n_traj = args.n_traj or 256
+        wname = "stress64_n1e4_1e6_powerlaw"
+    else:
+        mats = G.config_batch(1)
+        sched_name = args.batch_schedule
+        n_traj = args.n_traj or 4096
+        wname = "batch256_n30_400"
+    sched = P.preset(sched_name)
     bt = P.PermEstBatch(mats, device=0)
-    print(f"[bench] batch of {len(mats)} matrices, {n_traj} trajectories each, {args.batch_schedule}",
-          file=sys.stderr, flush=True)
+    if sched_name.startswith("learned"):
+        print(f"[bench] training the proposal network ({args.train_epochs} epochs)", file=sys.stderr, flush=True)
+        params, _ = LR.train_proposal(G.config_train(1), epochs=args.train_epochs, seed=args.seed)
+        bt.set_model(params, LR.MIX_ALPHA)
+    print(f"[bench] batch of {len(mats)} matrices (n {min(M.n for M in mats)}..{max(M.n for M in mats)}), "
+          f"{n_traj} trajectories each, {sched_name}", file=sys.stderr, flush=True)
     # set-up: preprocessing, autotuning and graph capture happen on the first runs
     for w in range(max(1, args.warmup)):
         bt.run(n_traj, args.seed + 1000 + w, sched, want_logw=False, want_alive=False, autotune=True, graph=True)
@@ -344,13 +405,22 @@ def batch_main(args) -> int:
     abytes = 0.0
     r0 = results[0]
     for M, r in zip(mats, r0):
-        scaled = sched.sk_policy in (1, 2, 3)
         abytes += r["n_traj"] * (24.0 * M.n + 9.0)
         abytes += r["n_full_sk"] * (18.0 * M.nnz + 16.0 * M.n) + r["n_dm"] * 27.0 * M.nnz
     wt = dict(r0[0])
     wt.update(n_steps=sum(r["n_steps"] for r in r0), n_traj=0, n_full_sk=0, n_dm=0)
-    abytes += algorithmic_bytes(wt, 0, 0, sched.sk_policy in (1, 2, 3))
+    abytes += algorithmic_bytes(wt, 0, 0, sched.sk_policy in (1, 2, 3, 4))
     achieved = abytes / kern_s / 1e9
+    # where the waves' time goes (device wall clock, summed over trajectories)
+    ws = sum(rs[0]["wave_seconds"] for rs in results)
+    phases = {"wave_seconds_per_launch": ws / len(results)}
+    for key, lab in (("wave_seconds_full_sk", "full_sk"), ("wave_seconds_dm", "inner_dm"),
+                     ("wave_seconds_local", "local_repair")):
+        phases[f"{lab}_frac"] = sum(rs[0][key] for rs in results) / ws if ws > 0 else None
+    if ws > 0:
+        phases["steps_frac"] = 1.0 - sum(v for k, v in phases.items() if k.endswith("_frac"))
+    n_dm_all = sum(r["n_dm"] for rs in results for r in rs)
+    phases["dm_entries_per_call"] = (sum(rs[0]["n_dm_entries"] for rs in results) / n_dm_all) if n_dm_all else None
     line = {
         "metric": f"effective samples/sec summed over a batch of {len(mats)} matrices",
         "value": ess / secs,
@@ -359,18 +429,239 @@ def batch_main(args) -> int:
         "ms_per_step": secs * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded generator)",
-        "config": {"workload": "batch256_n30_400", "matrices": len(mats), "n_traj_per_matrix": n_traj,
-                   "schedule": args.batch_schedule, "parallelism": "1 GPU", "autotune": True, "graph": True},
+        "config": {"workload": wname, "matrices": len(mats), "n_traj_per_matrix": n_traj,
+                   "n_total": int(sum(M.n for M in mats)), "nnz_total": int(sum(M.nnz for M in mats)),
+                   "schedule": sched_name, "parallelism": "1 GPU", "autotune": True, "graph": True},
         "estimate": {"trajectories_per_s": len(mats) * n_traj * args.steps / secs,
                      "steps_per_s": steps / secs, "ess_sum": ess,
                      "p_match_mean": float(np.mean([r["p_match"] for r in results[0]])),
-                     "n_dm": sum(r["n_dm"] for r in results[0]), "n_full_sk": sum(r["n_full_sk"] for r in results[0])},
+                     "n_dm": sum(r["n_dm"] for r in results[0]), "n_full_sk": sum(r["n_full_sk"] for r in results[0]),
+                     "phases": phases},
+        "launch": launch_shape(results[0][0]),
         "roofline": {"kernel": "pe::traj_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": abytes, "kernel_ms": kern_s * 1e3},
     }
     print(json.dumps(line), flush=True)
     bt.close()
+    return 0
+
+
+VARIANTS = ("fixed_all", "adaptive_threshold", "local_threshold", "adaptive_tracked", "local_tracked")
+
+
+def est_time(cps, eps):
+    """Time to target (Sec. 4 "Metrics"): the first checkpoint after the last
+    one whose relative error exceeds eps; None if the final one exceeds it."""
+    bad = [i for i, c in enumerate(cps) if not c["rel_error"] <= eps]
+    if bad and bad[-1] == len(cps) - 1:
+        return None
+    return cps[bad[-1] + 1 if bad else 0]
+
+
+def blocks_main(args) -> int:
+    """The variant study on the hidden-block set (Sec. 4, "Matrices used";
+    Sec. 4.2): the five variants of Sec. 4 on the 50 regenerated
+    block-diagonal matrices of exactly known permanent (stored references),
+    all 50 in one batched launch per checkpoint.  Each variant runs rounds of
+    doubling trajectory counts per matrix (256, 256, 512, ...; a new run
+    seed per round, estimates pooled over rounds) until its time budget is
+    spent; after every round each matrix's relative error, RSE and p_match
+    are logged with the variant's cumulative GPU time.  Reported per
+    variant as in the paper's summary: error and RSE wins, median RSE,
+    minimum p_match, median M, and the time to relative error 1e-3 and 1e-2
+    (matrices stabilised, median time and trajectories)."""
+    import torch
+
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+
+    with open(os.path.join(ROOT, "tests", "golden", "blocks50.json")) as f:
+        ref = {m["name"]: m for m in json.load(f)["matrices"]}
+    sets = list(G.config_blocks())
+    for name, M, _ in sets:
+        r = ref[name]
+        h = hashlib.sha256()
+        for a in (M.row_ptr, M.col_idx, M.col_ptr, M.row_idx):
+            h.update(a.astype("<i4").tobytes())
+        if h.hexdigest() != r["index_sha256"]:
+            raise SystemExit(f"bench.py: the generator no longer builds the stored block matrix {name}")
+    mats = [M for _, M, _ in sets]
+    names = [nm for nm, _, _ in sets]
+    lp = np.array([ref[nm]["log_permanent"] for nm in names])
+    per_var = {}
+    for vname in VARIANTS:
+        sched = P.preset(vname)
+        bt = P.PermEstBatch(mats, device=0)
+        bt.run(8, args.seed + 999, sched, want_logw=False, want_alive=False)  # preprocessing
+        torch.cuda.synchronize()
+        lws = [[] for _ in mats]
+        als = [[] for _ in mats]
+        cps = [[] for _ in mats]
+        spent, rnd, count = 0.0, 0, 256
+        while spent < args.block_seconds:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = bt.run(count, args.seed + rnd, sched, autotune=True)
+            torch.cuda.synchronize()
+            spent += time.perf_counter() - t0
+            lw = out["logw"].cpu().numpy()
+            al = out["alive"].cpu().numpy().astype(bool)
+            off = out["offsets"]
+            for b in range(len(mats)):
+                lws[b].append(lw[off[b]:off[b + 1]])
+                als[b].append(al[off[b]:off[b + 1]])
+                st = pooled(np.concatenate(lws[b]), np.concatenate(als[b]), spent)
+                le = st["log_estimate"]
+                cps[b].append({"seconds": spent, "trajectories": st["n_traj"],
+                               "rel_error": abs(math.expm1(le - lp[b])) if math.isfinite(le) else 1.0,
+                               "rse": st["rse"], "p_match": st["p_match"]})
+            print(f"[bench]   blocks {vname}: round {rnd + 1}, {count} per matrix, {spent:.1f} s",
+                  file=sys.stderr, flush=True)
+            rnd += 1
+            count = count if rnd == 1 else 2 * count
+        bt.close()
+        per_var[vname] = cps
+    # summary in the form of the paper's variant table
+    V, B = len(VARIANTS), len(mats)
+    fin_err = np.array([[per_var[v][b][-1]["rel_error"] for b in range(B)] for v in VARIANTS])
+    fin_rse = np.array([[per_var[v][b][-1]["rse"] for b in range(B)] for v in VARIANTS])
+    summary_rows = {}
+    for i, v in enumerate(VARIANTS):
+        row = {"error_wins": int(np.sum(np.argmin(fin_err, axis=0) == i)),
+               "rse_wins": int(np.sum(np.nanargmin(np.where(np.isnan(fin_rse), np.inf, fin_rse), axis=0) == i)),
+               "median_rse": float(np.nanmedian(fin_rse[i])),
+               "min_p_match": float(min(per_var[v][b][-1]["p_match"] for b in range(B))),
+               "median_M": float(np.median([per_var[v][b][-1]["trajectories"] for b in range(B)])),
+               "seconds": per_var[v][0][-1]["seconds"]}
+        for eps in (1e-3, 1e-2):
+            hits = [est_time(per_var[v][b], eps) for b in range(B)]
+            got = [h for h in hits if h is not None]
+            row[f"est_{eps:g}"] = {"reached": len(got), "of": B,
+                                   "median_seconds": float(np.median([h["seconds"] for h in got])) if got else None,
+                                   "median_trajectories": float(np.median([h["trajectories"] for h in got]))
+                                   if got else None}
+        summary_rows[v] = row
+        print(f"[bench]   {v}: {row}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "hidden-block variant study: matrices stabilised at relative error 1e-3 within the budget",
+        "value": summary_rows["local_threshold"]["est_0.001"]["reached"],
+        "unit": "matrices of 50",
+        "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator; exact permanents stored in tests/golden/blocks50.json)",
+        "config": {"workload": "blocks50", "variants": list(VARIANTS), "budget_seconds_per_variant": args.block_seconds,
+                   "launch": "50 matrices per batched launch, autotuned"},
+        "variants": summary_rows,
+        "per_matrix_final": {v: [{"name": names[b], **per_var[v][b][-1]} for b in range(B)] for v in VARIANTS},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+CONSENSUS_SETS = {
+    # n = 1e3, the large workload's family (avg degree 8): the five variants of Sec. 4
+    "n1e3": {"n": 1000, "variants": VARIANTS, "n_traj": 16384},
+    # the large workload itself (n = 1e5): the methods that run there
+    "n1e5": {"n": 100_000, "variants": ("local_nodm", "learned", "learned_gated"), "n_traj": 4000},
+}
+
+
+def consensus_main(args) -> int:
+    """Multi-seed consensus diagnostics (Sec. 4.4) for matrices whose
+    permanent is not known: V variants x 5 run seeds on one matrix of the
+    large workload's family at n = 1e3 (the five variants of Sec. 4) and on
+    the n = 1e5 matrix itself (local repair, learned proposal with and
+    without its gated fallback), each run a fixed number of trajectories;
+    the library's perm_est_consensus gives the equal-variant consensus, its
+    relative half-width, the variant ratio, D_max against the Bonferroni
+    value and the provisional-consensus checks."""
+    import torch
+
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+    from paper_2608_15390_amd import learned as LR
+
+    params = None
+    out = {}
+    for tag, cfg in CONSENSUS_SETS.items():
+        M = G.planted_uniform(cfg["n"], 7 * cfg["n"], 5) if cfg["n"] < 100_000 else G.config_large(1)
+        if any(v.startswith("learned") for v in cfg["variants"]) and params is None:
+            params, _ = LR.train_proposal(G.config_train(1), epochs=args.train_epochs, seed=args.seed)
+        est = P.PermEst(M, device=0)
+        if params is not None:
+            est.set_model(params, LR.MIX_ALPHA)
+        runs, secs = [], {}
+        for v in cfg["variants"]:
+            sched = P.preset(v)
+            est.run(0, 64, args.seed, sched, want_logw=False, want_alive=False)
+            row, t = [], 0.0
+            for r in range(args.consensus_seeds):
+                res, s = timed_run(est, 0, cfg["n_traj"], 1000 + r, sched)
+                row.append(res["result"])
+                t += s
+            runs.append(row)
+            secs[v] = t
+            print(f"[bench]   consensus {tag} {v}: {args.consensus_seeds} seeds, {t:.1f} s", file=sys.stderr,
+                  flush=True)
+        est.close()
+        c = P.consensus(runs)
+        c["variants"] = list(cfg["variants"])
+        c["n"] = M.n
+        c["n_traj_per_run"] = cfg["n_traj"]
+        c["seconds_per_variant"] = secs
+        c["runs"] = [[{k: r[k] for k in ("log_estimate", "rse", "ess", "p_match", "n_alive")} for r in row]
+                     for row in runs]
+        out[tag] = c
+    line = {
+        "metric": "multi-seed consensus: relative 95% half-width of the equal-variant consensus",
+        "value": out["n1e3"]["rel_half_width"], "unit": "relative", "n_gpus": 1,
+        "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator)",
+        "config": {"workload": "consensus", "seeds": args.consensus_seeds}, "consensus": out,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def hubs_main(args) -> int:
+    """The bounded-work local repair on hub vertices (Sec. 3.3): a power-law
+    matrix (row degrees P(d) ~ d^-2.5 on [2, 200] plus a planted
+    permutation), the plain scaled method (`local_nodm`) with the exact
+    repair of Eq. (local) and with caps B on the list entries examined, the
+    same trajectory ids and seed for each; per cap the trajectories/s, the
+    entries examined per repair, ESS/s and Var ln X."""
+    import paper_2608_15390_amd as P
+    from paper_2608_15390_amd import inputs as G
+
+    n = args.hub_n
+    M = G.power_law(n, 7)
+    est = P.PermEst(M, device=0)
+    count = args.n_traj or 20_000
+    rows = []
+    for cap in (0, 32, 16, 8, 4):
+        sched = P.preset("local_nodm", local_cap=cap)
+        est.run(count, 64, args.seed, sched, want_logw=False, want_alive=False)
+        out, secs = timed_run(est, 0, count, args.seed, sched, want=True)
+        r = out["result"]
+        st = pooled(out["logw"].cpu().numpy(), out["alive"].cpu().numpy().astype(bool), secs, r["n_steps"])
+        rows.append({"local_cap": cap, "seconds": secs, "traj_per_s": count / secs,
+                     "entries_per_repair": r["n_local_entries"] / max(r["n_local_sk"], 1),
+                     "values_per_repair": r["n_local_values"] / max(r["n_local_sk"], 1),
+                     "ess": st["ess"], "ess_per_s": st["ess"] / secs, "var_logw": st["var_logw"],
+                     "p_match": st["p_match"], "log_estimate": st["log_estimate"],
+                     "local_seconds_frac": r["wave_seconds_local"] / r["wave_seconds"] if r["wave_seconds"] else None})
+        print(f"[bench]   hubs cap={cap}: {rows[-1]['traj_per_s']:.0f} traj/s, "
+              f"{rows[-1]['entries_per_repair']:.0f} entries/repair, ESS {st['ess']:.1f}", file=sys.stderr, flush=True)
+    est.close()
+    line = {
+        "metric": "bounded-work local repair on a power-law matrix: trajectories/s by cap",
+        "value": rows[2]["traj_per_s"], "unit": "trajectories/s (cap 16)", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator)",
+        "config": {"workload": f"powerlaw_n{n}_dmax200", "n": M.n, "nnz": M.nnz, "n_traj": count,
+                   "max_row_degree": int(np.diff(M.row_ptr).max()), "schedule": "local_nodm"},
+        "caps": rows,
+    }
+    print(json.dumps(line), flush=True)
     return 0
 
 
@@ -435,14 +726,22 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10,
                     help="timed steps; the job's trajectory ids are split evenly over them")
     ap.add_argument("--warmup", type=int, default=1, help="untimed steps on trajectory ids beyond the job's")
-    ap.add_argument("--workload", default="large", choices=["large", "small", "batch"],
-                    help="batch: 256 matrices n in [30, 400] in one persistent, autotuned, graph-replayed launch")
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "small", "batch", "stress", "blocks", "consensus", "hubs"],
+                    help="batch: 256 matrices n in [30, 400] in one persistent, autotuned, graph-replayed launch; "
+                         "blocks: the five variants on the 50-matrix hidden-block set (exact permanents); "
+                         "consensus: multi-seed consensus diagnostics on matrices of unknown permanent")
+    ap.add_argument("--block-seconds", type=float, default=30.0, help="GPU time budget per variant (blocks)")
+    ap.add_argument("--consensus-seeds", type=int, default=5, help="run seeds per variant (consensus)")
+    ap.add_argument("--hub-n", type=int, default=20_000, help="order of the power-law matrix (hubs)")
     ap.add_argument("--batch-schedule", default="adaptive_threshold")
     ap.add_argument("--method", default="learned", choices=["learned", "plain"],
                     help="method whose job is timed as `value`")
     ap.add_argument("--plain-schedule", default="local_nodm")
     ap.add_argument("--learned-schedule", default="learned")
     ap.add_argument("--n-traj", type=int, default=None, help="trajectories of the whole job")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="launches in flight together (one handle and HIP stream each)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-compare", action="store_true", help="skip the other method, the ladder and the band")
@@ -479,8 +778,14 @@ def main() -> int:
         print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         return 2
 
-    if args.workload == "batch":
+    if args.workload in ("batch", "stress"):
         return batch_main(args)
+    if args.workload == "blocks":
+        return blocks_main(args)
+    if args.workload == "consensus":
+        return consensus_main(args)
+    if args.workload == "hubs":
+        return hubs_main(args)
 
     import torch
 
@@ -511,46 +816,45 @@ def main() -> int:
         params, tinfo = LR.train_proposal(G.config_train(1), epochs=args.train_epochs, seed=args.seed)
     if args.save_model:
         P.save_model(args.save_model, params, LR.MIX_ALPHA)
-    est = P.PermEst(M, device=0)
-    est.set_model(params, LR.MIX_ALPHA)
+    # one handle per stream: launches on different handles run concurrently
+    n_streams = max(1, min(args.streams, args.steps))
+    ests = [P.PermEst(M, device=0) for _ in range(n_streams)]
+    for e in ests:
+        e.set_model(params, LR.MIX_ALPHA)
+    streams = [torch.cuda.Stream() for _ in ests]
+    est = ests[0]
     # the job's ids split over the timed steps; warmup on ids beyond the job
     chunk = -(-n_job // args.steps)
     ranges = [(k * chunk, min(chunk, n_job - k * chunk)) for k in range(args.steps) if k * chunk < n_job]
     # preprocessing (initial filter, outer SK, templates) happens on the first run
-    est.run(n_job + args.warmup * chunk, 64, args.seed, sched, want_logw=False, want_alive=False)
+    for e in ests:
+        e.run(n_job + args.warmup * chunk, 64, args.seed, sched, want_logw=False, want_alive=False)
     torch.cuda.synchronize()
 
     print(f"[bench] {args.warmup} warmup + {len(ranges)} timed steps of {chunk} trajectories, "
-          f"{args.method} on {wname}", file=sys.stderr, flush=True)
-    for w in range(args.warmup):
-        est.run(n_job + w * chunk, chunk, args.seed, sched, want_logw=False, want_alive=False)
+          f"{args.method} on {wname}, {n_streams} in flight", file=sys.stderr, flush=True)
+    if args.warmup:
+        wr = [(n_job + w * chunk, chunk) for w in range(args.warmup)]
+        run_concurrent(ests, wr, args.seed, sched, streams, "warmup", want=False)
         torch.cuda.synchronize()
-        print(f"[bench]   warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
-    outs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k, (first, cnt) in enumerate(ranges):
-        outs.append(est.run(first, cnt, args.seed, sched, want_logw=True, want_alive=True))
-        if (k + 1) % max(1, len(ranges) // 10) == 0:
-            print(f"[bench]   step {k + 1}/{len(ranges)}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
+    job, secs, results, lw, al = timed_concurrent(ests, ranges, args.seed, sched, streams, "timed")
     ms_per_step = secs * 1e3 / len(ranges)
-    lw = np.concatenate([o["logw"].cpu().numpy() for o in outs])
-    al = np.concatenate([o["alive"].cpu().numpy() for o in outs]).astype(bool)
-    results = [o["result"] for o in outs]
-    job = pooled(lw, al, secs, sum(r["n_steps"] for r in results))
     value = job["ess"] / secs
 
-    # roofline of the trajectory kernel: algorithmic bytes per launch over its
-    # average device time (HIP events around the kernel on the run's stream)
+    # roofline of the trajectory kernel.  Each launch's device time comes
+    # from HIP events around the kernel on its own stream; with several
+    # launches in flight they overlap, so the chip-wide rate is the
+    # algorithmic bytes of all timed launches over the time the kernels
+    # were in flight together (their summed device time over the launches
+    # in flight, never more than the timed wall time)
     kern_s = sum(r["kernel_seconds"] for r in results) / len(results)
+    in_flight = min(n_streams, len(ranges))
+    busy_s = min(secs, sum(r["kernel_seconds"] for r in results) / in_flight)
     scaled = sched.sk_policy in (1, 2, 3, 4)
     abytes = sum(algorithmic_bytes(r, M.n, M.nnz, scaled) for r in results) / len(results)
-    achieved = abytes / kern_s / 1e9
-    tiles = sum(r["n_mlp_tiles"] for r in results) / len(results)
-    mfma_tflops = tiles * FLOP_PER_TILE / kern_s / 1e12
+    achieved = abytes * len(results) / busy_s / 1e9
+    tiles = sum(r["n_mlp_tiles"] for r in results)
+    mfma_tflops = tiles * FLOP_PER_TILE / busy_s / 1e12
     traffic = load_traffic(f"{wname}_{args.method}", chunk)
     mine = summary(job, secs)
     mine["time_to_rse"] = job["time_to_rse"]
@@ -571,6 +875,7 @@ def main() -> int:
         "data": "synthetic (seeded generator)",
         "config": {
             "workload": wname, "n": M.n, "nnz": M.nnz, "n_traj": n_job, "n_traj_per_step": chunk,
+            "launches_in_flight": in_flight,
             "method": args.method, "schedule": sched_name, "parallelism": "1 GPU",
             "arithmetic": "f64 weights and statistics, f32 scaling, bf16 network on an exact grid",
         },
@@ -578,20 +883,23 @@ def main() -> int:
         "training": dict(tinfo, matrices="512 x (n=1000, avg degree 6)", teacher="local_nodm (local SK repair per step)",
                          mix_alpha=LR.MIX_ALPHA),
         "roofline": {
-            "kernel": "pe::traj_kernel",
+            "kernel": KERNEL_NAME.get(args.method, "pe::traj_kernel"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            # the measured HBM bytes over the same launch time, and as a
-            # fraction of the peak (null with `traffic`)
-            "traffic_gbs": traffic / kern_s / 1e9 if traffic else None,
-            "traffic_frac": traffic / kern_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+            # the measured HBM bytes of all timed launches over the same
+            # in-flight time, and as a fraction of the peak (null with `traffic`)
+            "traffic_gbs": traffic * len(results) / busy_s / 1e9 if traffic else None,
+            "traffic_frac": traffic * len(results) / busy_s / 1e9 / HBM_PEAK_GBS if traffic else None,
             "algorithmic_bytes_per_launch": abytes,
             "n_traj_per_launch": chunk,
+            "launches_in_flight": in_flight,
             "kernel_ms": kern_s * 1e3,
+            "in_flight_seconds": busy_s,
+            "launch": launch_shape(results[0]),
             "mfma_bf16_tflops": mfma_tflops,
             "mfma_frac": mfma_tflops / MFMA_BF16_PEAK_TFLOPS,
         },
@@ -601,8 +909,9 @@ def main() -> int:
         other = plain_sched if args.method == "learned" else learned_sched
         oname = "plain" if args.method == "learned" else "learned"
         print(f"[bench] comparison run: {oname}, same trajectory ids in the same steps", file=sys.stderr, flush=True)
-        est.run(n_job + args.warmup * chunk, 64, args.seed, other, want_logw=False, want_alive=False)
-        res_o, secs_o, _ = chunked_run(est, ranges, args.seed, other, oname)
+        for e in ests:
+            e.run(n_job + args.warmup * chunk, 64, args.seed, other, want_logw=False, want_alive=False)
+        res_o, secs_o, _, _, _ = timed_concurrent(ests, ranges, args.seed, other, streams, oname)
         theirs = summary(res_o, secs_o)
         theirs["time_to_rse"] = res_o["time_to_rse"]
         learned_s, plain_s = (mine, theirs) if args.method == "learned" else (theirs, mine)
@@ -625,7 +934,8 @@ def main() -> int:
         line["cpu_baseline"] = cpu_leg(args, M, params, sched_name, chunk, lw, al.astype(np.uint8),
                                        job["ess"], n_job)
     print(json.dumps(line), flush=True)
-    est.close()
+    for e in ests:
+        e.close()
     return 0
 
 

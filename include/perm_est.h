@@ -109,7 +109,21 @@ typedef struct {
                              and the next step draws from the scaled
                              proposal of Eq. (q) with z = r_rho c_gam
                              instead of the network.  0 = network only    */
-    int32_t reserved[3];  /* must be 0                                      */
+    int32_t local_cap;    /* local repair (PE_SK_LOCAL, or the gated learned
+                             fallback; else must be 0): 0 = Eq. (local)
+                             exactly; B in [1, 65535] = bounded work for hub
+                             vertices (Sec. 3.3 proposes it): a list of
+                             L > B entries is examined at the B positions
+                             (o + floor(k L / B)) mod L, k = 0..B-1, with
+                             o = floor(R L / 2^32), R the low 32 bits of the
+                             trajectory's draw (step t, draw 2^31 + vertex
+                             id); its active entries stand for the vertex's
+                             child neighbourhood in the two-hop sets, and
+                             its new value is 1 / (sampled sum * residual
+                             degree / sampled active count) (unchanged when
+                             nothing active was sampled).  Lists of at most
+                             B entries are used whole                     */
+    int32_t reserved[2];  /* must be 0                                      */
 } perm_est_schedule;
 
 typedef struct {
@@ -142,6 +156,21 @@ typedef struct {
     double kernel_seconds;     /* device time of the trajectory kernel alone
                                   (HIP events on the run's stream); equal to
                                   `seconds` for a replayed graph            */
+    /* device time by phase, summed over the trajectories of the launch (each
+       trajectory's wave reads the device wall clock; one trajectory per
+       wave -- the kernels that run four per wave leave these 0) */
+    double wave_seconds;          /* whole trajectories                      */
+    double wave_seconds_full_sk;  /* full SK sweeps (Fixed, Adaptive)        */
+    double wave_seconds_dm;       /* inner DM calls                          */
+    double wave_seconds_local;    /* local repairs                           */
+    int64_t n_dm_entries;         /* adjacency entries the inner DM calls
+                                     examined (augmentation and SCC)         */
+    /* the launch shape used */
+    int32_t launch_blocks;            /* persistent workgroups               */
+    int32_t launch_waves_per_block;
+    int32_t launch_trajectories_per_wave; /* 1, or 4 (16-lane rows)       */
+    int32_t launch_blocks_per_cu;     /* resident workgroups per CU the
+                                         launch was sized for              */
 } perm_est_result;
 
 /* Create a handle for one n x n matrix A given in both CSR and CSC form

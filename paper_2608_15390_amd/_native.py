@@ -29,7 +29,8 @@ class Schedule(C.Structure):
         ("theta_th", C.c_double),
         ("theta_tr", C.c_double),
         ("local_gate", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("local_cap", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
     def as_dict(self):
@@ -59,6 +60,15 @@ class Result(C.Structure):
         ("n_mlp_tiles", C.c_int64),
         ("n_entries_scanned_v", C.c_int64),
         ("kernel_seconds", C.c_double),
+        ("wave_seconds", C.c_double),
+        ("wave_seconds_full_sk", C.c_double),
+        ("wave_seconds_dm", C.c_double),
+        ("wave_seconds_local", C.c_double),
+        ("n_dm_entries", C.c_int64),
+        ("launch_blocks", C.c_int32),
+        ("launch_waves_per_block", C.c_int32),
+        ("launch_trajectories_per_wave", C.c_int32),
+        ("launch_blocks_per_cu", C.c_int32),
     ]
 
     def as_dict(self):

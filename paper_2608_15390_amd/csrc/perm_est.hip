@@ -115,7 +115,11 @@ struct Tune {
 
 }  // namespace
 
-constexpr int kWorkTotals = 7;  // launch-wide work counters, see BatchArgs::work_totals
+constexpr int kWorkTotals = 12;
+// bytes of a min-tree's lowest internal level above which it lives in the
+// trajectory's state slot (one trajectory per wave, HBM tier); 1024 nodes
+// = 2^18 leaves, i.e. n above 131072
+constexpr size_t kTreeLevel0LdsMax = 4096;  // launch-wide work counters, see BatchArgs::work_totals
 
 // Scratch of perm_est_run_range_noalloc: one array per GPU the library runs
 // on, held until the process ends.  Host code never uses this name as an
@@ -150,6 +154,7 @@ struct perm_est {
     int device = 0;
     uint32_t opt_flags = 0;
     int cu_count = 256;
+    double wall_hz = 0.0;  // rate of the device wall clock the kernels read
     size_t lds_block = 64 * 1024;  // LDS one workgroup may allocate (queried)
     size_t lds_cu = 160 * 1024;    // LDS of one compute unit
     std::vector<MatData> mats;
@@ -527,7 +532,10 @@ int check_schedule(const perm_est_schedule *s) {
     if (s->local_gate < 0 || s->local_gate > 1) return fail(PE_EINVAL, "bad local_gate");
     if (s->local_gate && s->sk_policy != PE_SK_LEARNED)
         return fail(PE_EINVAL, "local_gate applies to the learned proposal only");
-    for (int i = 0; i < 3; ++i)
+    if (s->local_cap < 0 || s->local_cap > 65535) return fail(PE_EINVAL, "local_cap must lie in [0, 65535]");
+    if (s->local_cap && !(s->sk_policy == PE_SK_LOCAL || (s->sk_policy == PE_SK_LEARNED && s->local_gate)))
+        return fail(PE_EINVAL, "local_cap applies to the local repair only");
+    for (int i = 0; i < 2; ++i)
         if (s->reserved[i] != 0) return fail(PE_EINVAL, "reserved schedule fields must be 0");
     return PE_OK;
 }
@@ -593,6 +601,9 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess && wall_khz > 0)
+        h->wall_hz = 1e3 * (double)wall_khz;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lds > 0)
         h->lds_block = (size_t)lds;
@@ -759,6 +770,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.sk_policy = sched->sk_policy;
         a.dm_policy = sched->dm_policy;
         a.K = sched->K;
+        a.local_cap = sched->local_cap;
         a.scaled = gated || (!learned && ((P->r0 != nullptr) || own_rc));
         a.theta_th = sched->theta_th;
         a.theta_tr = sched->theta_tr;
@@ -804,7 +816,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     }
 
     // ---- tier and launch shape
-    const size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
+    size_t tree_bytes = ((size_t)tree_total * 4 + 15) / 16 * 16;
     const size_t kLdsBlock = h->lds_block, kLdsCU = h->lds_cu;
     // per-matrix tier: a matrix whose state fits beside the tree in 32 KB runs
     // in LDS, unless such matrices carry under half of the launch's work (then
@@ -854,6 +866,37 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
                                        block_fixed + 4 * tree_bytes + (size_t)lds_cap <= kLdsBlock);
     const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt) : rows_kernel_fn(wt);
     const int tpw = rows ? 4 : 1;  // trajectories per wave
+    // One trajectory per wave: a large matrix keeps the lowest internal level
+    // of its min-tree (one node per 256 leaves, the bulk of the tree) in its
+    // state slot and only the levels above in LDS, so the LDS a wave reserves
+    // no longer grows with n and large orders keep their occupancy.
+    if (!rows) {
+        int32_t lds_total = 0;
+        for (size_t b = 0; b < count; ++b) {
+            TrajArgs &a = h->args_host[b];
+            const TreeLayout &full = prep[b]->tree;
+            if (!a.lds_tier && full.levels >= 2 && (size_t)full.size[0] * 4 > kTreeLevel0LdsMax) {
+                const uint64_t at = (mat_bytes[b] + 255) / 256 * 256;
+                const uint64_t end = (at + 4ull * full.size[0] + 255) / 256 * 256;
+                if (end >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
+                a.st.lvl0 = (uint32_t)at;
+                a.st.bytes = (uint32_t)end;
+                mat_bytes[b] = end;
+                hbm_cap = std::max<uint64_t>(hbm_cap, end);
+                a.l0_state = 1;
+                a.tree_l1_src = full.off[1];
+                TreeLayout up = full;  // LDS holds levels 1.. only
+                int32_t o = 0;
+                up.off[0] = 0;
+                for (int k = 1; k < full.levels; ++k) { up.off[k] = o; o += full.size[k]; }
+                up.total = (o + 3) / 4 * 4;
+                a.tree = up;
+            }
+            lds_total = std::max(lds_total, a.tree.total);
+        }
+        tree_bytes = ((size_t)lds_total * 4 + 15) / 16 * 16;
+        B.lds_tree_bytes = (int32_t)tree_bytes;
+    }
     size_t per_wave = rows_learned ? 4 * tree_bytes + (size_t)kRowNetScratchBytes
                                    : (size_t)tpw * tree_bytes + (size_t)B.lds_mlp_bytes + (size_t)lds_cap;
     int wpb = wpb_req > 0 ? wpb_req : 4;
@@ -1024,15 +1067,29 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
             r.n_local_values = (int64_t)wt_tot[3];
             r.n_mlp_tiles = (int64_t)wt_tot[5];
             r.n_entries_scanned_v = (int64_t)wt_tot[6];
+            const double tick = h->wall_hz > 0 ? 1.0 / h->wall_hz : 0.0;
+            r.wave_seconds = (double)wt_tot[7] * tick;
+            r.wave_seconds_full_sk = (double)wt_tot[8] * tick;
+            r.wave_seconds_dm = (double)wt_tot[9] * tick;
+            r.wave_seconds_local = (double)wt_tot[10] * tick;
+            r.n_dm_entries = (int64_t)wt_tot[11];
+            r.launch_blocks = (int32_t)blocks;
+            r.launch_waves_per_block = wpb;
+            r.launch_trajectories_per_wave = tpw;
+            r.launch_blocks_per_cu = (int32_t)per_cu;
             r.kernel_seconds = kms * 1e-3;
         }
     }
     return PE_OK;
 }
 
-// Launch-shape autotuner: time candidate (waves per block, blocks per CU)
+// Launch-shape autotuner: run candidate (waves per block, blocks per CU)
 // pairs on a probe range of trajectories (results are identical for every
-// shape) and keep the fastest per (schedule kind, tier).
+// shape) and keep the best per (schedule kind, tier).  A probe's elapsed
+// time is set by its longest trajectories (large matrices run 1e6 steps),
+// which favours low occupancy; so where the kernel reports its waves' device
+// time, a shape is scored by its steady-state rate instead: the waves it
+// keeps resident (up to the probe's size) over the mean wave time per step.
 int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, const std::vector<RunPart> &parts,
                 hipStream_t s, int *wpb, int *per_cu) {
     const int force = (h->opt_flags & PE_FLAG_FORCE_HBM) ? 1 : 0;
@@ -1056,13 +1113,26 @@ int tuned_shape(perm_est *h, const perm_est_schedule *sched, uint64_t seed, cons
     double best = 1e300;
     Tune tb;
     tb.sk = sk_kind; tb.dm = sched->dm_policy != 0; tb.force_hbm = force;
+    int64_t probe_items = 0;
+    for (auto &p : probe) probe_items += p.count;
+    std::vector<perm_est_result> rr(parts.size());
     for (int w : cand_wpb)
         for (int c : cand_cu) {
             const int per_cu_blocks = std::max(1, c / w);
             double ms = 0;
-            int rc = launch(h, sched, seed, probe, nullptr, s, w, per_cu_blocks, &ms);
+            int rc = launch(h, sched, seed, probe, rr.data(), s, w, per_cu_blocks, &ms);
             if (rc) return rc;
-            if (ms < best) { best = ms; tb.wpb = w; tb.per_cu = per_cu_blocks; }
+            int64_t steps = 0;
+            for (auto &r : rr) steps += r.n_steps;
+            const perm_est_result &r0 = rr[0];
+            double score = ms;
+            if (r0.wave_seconds > 0.0 && steps > 0) {
+                const int64_t tpw = std::max(1, r0.launch_trajectories_per_wave);
+                const int64_t capacity = (int64_t)h->cu_count * r0.launch_blocks_per_cu * r0.launch_waves_per_block;
+                const int64_t resident = std::max<int64_t>(1, std::min(capacity, (probe_items + tpw - 1) / tpw));
+                score = r0.wave_seconds / (double)steps / (double)resident;
+            }
+            if (score < best) { best = score; tb.wpb = w; tb.per_cu = per_cu_blocks; }
         }
     h->tunes.push_back(tb);
     *wpb = tb.wpb;

@@ -54,6 +54,7 @@ struct TreeLayout {
 
 struct StateLayout {  // byte offsets in one trajectory's state block
     uint32_t deg, rec, lst_a, lst_b, loc_r, loc_c, new_v, rem, mate_r, mate_c, ws;
+    uint32_t lvl0;   // the min-tree's lowest internal level, when TrajArgs::l0_state
     uint32_t bytes;
 };
 
@@ -78,11 +79,14 @@ struct TrajArgs {
     const int32_t *mate0_r;    // perfect matching of the filtered input, or nullptr
     const int32_t *mate0_c;
     int32_t n_leaf;
-    TreeLayout tree;
+    TreeLayout tree;           // the internal levels the wave keeps in LDS (offsets there)
+    int32_t l0_state;          // 1: level 0 lives in the state slot (st.lvl0), LDS holds levels 1..
+    int32_t tree_l1_src;       // with l0_state: u32 offset of level 1 in the tree templates
     StateLayout st;
     int32_t ok0;               // 0: the input has no perfect matching
     int32_t lds_tier;          // 1: this matrix's state lives in the wave's LDS slot
     int32_t vertex_rule, sk_policy, dm_policy, K;
+    int32_t local_cap;         // bounded-work local repair: 0 = Eq. (local) exactly
     int32_t scaled;            // proposal uses r/c
     double theta_th, theta_tr;
     uint64_t seed;
@@ -111,6 +115,21 @@ struct TrajArgs {
     int32_t rec_stride;
 };
 
+// Bounded-work local repair: a list of L > cap entries is examined at the
+// cap positions (o + floor(i L / cap)) mod L, i = 0..cap-1 (a systematic
+// sample; distinct since L / cap > 1), with the offset o = floor(R L / 2^32)
+// from the low 32 bits R of the trajectory's draw 2^31 + x at step t.
+// L <= 65534 and cap <= 65535 keep i * L below 2^32.
+__device__ __forceinline__ uint32_t sample_offset(uint64_t seed, uint32_t k, uint32_t b, uint32_t t, int32_t x,
+                                                  int32_t L) {
+    const uint32_t R = (uint32_t)rand64(seed, k, b, t, 0x80000000u | (uint32_t)x);
+    return (uint32_t)(((uint64_t)R * (uint64_t)(uint32_t)L) >> 32);
+}
+__device__ __forceinline__ int32_t sample_pos(uint32_t o, int32_t i, int32_t L, int32_t cap) {
+    const uint32_t p = o + ((uint32_t)i * (uint32_t)L) / (uint32_t)cap;
+    return (int32_t)(p >= (uint32_t)L ? p - (uint32_t)L : p);
+}
+
 // ------------------------------------------------------------------ views
 // AS: address space of the trajectory's state (kAsLds: the wave's LDS
 // slot, kAsGlobal: its HBM slot)
@@ -126,11 +145,13 @@ struct Traj {
     as_ptr<AS, float> new_v;
     as_ptr<AS, uint32_t> rem;
     as_ptr<AS, int32_t> mate_r, mate_c, ws;
+    uint32_t *lvl0;  // the tree's lowest internal level (LDS, or the state slot)
     int32_t n;
 
     __device__ Traj(const PE_G TrajArgs &args, char *state_any, uint32_t *tree_lds)
         : a(args), M(args.A), r0(gptr(args.r0)), c0(gptr(args.c0)), tree(tree_lds), n(args.A.n) {
         const auto &s = args.st;
+        lvl0 = args.l0_state ? reinterpret_cast<uint32_t *>(state_any + s.lvl0) : tree_lds + args.tree.off[0];
         const auto state = to_as<AS>(state_any);
         deg = recast<uint16_t>(state + s.deg);
         rec = OWN ? recast<Rec>(state + s.rec) : nullptr;
@@ -174,7 +195,7 @@ struct Traj {
     }
 
     // ------------------------------------------------------ min-tree
-    __device__ __forceinline__ uint32_t *level(int k) const { return tree + a.tree.off[k]; }
+    __device__ __forceinline__ uint32_t *level(int k) const { return k == 0 ? lvl0 : tree + a.tree.off[k]; }
 
     __device__ __forceinline__ void tree_lower(int32_t x, uint32_t d) const {
         atomicMin(level(0) + (x >> 8), d);
@@ -357,6 +378,34 @@ struct Traj {
         return acc;
     }
 
+    // Bounded-work form of residual_sum for a list longer than cap: the sum
+    // of B_xy * s_y over the active entries at the cap sample positions of
+    // x's list (offset o, sample order, binary32, no FMA) and their count.
+    __device__ float sampled_sum(int32_t x, uint32_t o, int32_t cap, int32_t &cnt) const {
+        const bool row = x < n;
+        int32_t beg, end;
+        list(x, beg, end);
+        const int32_t L = end - beg;
+        float acc = 0.0f;
+        int32_t c = 0;
+        for (int32_t i = 0; i < cap; ++i) {
+            const int32_t p = beg + sample_pos(o, i, L, cap);
+            const int32_t y = row ? n + M.col_idx[p] : M.row_idx[p];
+            const float sv = rec[y].s;
+            if (!(sv >= 0.0f)) continue;
+            if (DM) {
+                const int32_t e = row ? p : M.csc2csr[p];
+                if (removed(e)) continue;
+            }
+            const float bv = WT ? (row ? M.val[p] : M.val_csc[p]) : 1.0f;
+            const float prod = bv * sv;
+            acc = acc + prod;
+            ++c;
+        }
+        cnt = c;
+        return acc;
+    }
+
     // ------------------------------------------------- inner support filter
     // Alg. 2 InnerDM on the child residual: repair the kept perfect matching
     // (one BFS augmentation per row that lost its partner), strongly
@@ -368,12 +417,13 @@ struct Traj {
     // perfect matching.
     __device__ bool augment_from(int32_t s, as_ptr<AS, int32_t> queue, as_ptr<AS, int32_t> parent,
                                  as_ptr<AS, int32_t> vis,
-                                 int32_t stamp) const {
+                                 int32_t stamp, uint64_t &examined) const {
         int32_t head = 0, tail = 0, found = -1;
         queue[tail++] = s;
         while (head < tail && found < 0) {
             const int32_t i = queue[head++];
             for (int32_t e = M.row_ptr[i]; e < M.row_ptr[i + 1]; ++e) {
+                ++examined;
                 const int32_t j = M.col_idx[e];
                 if (!active(n + j) || removed(e) || vis[j] == stamp) continue;
                 vis[j] = stamp;
@@ -395,21 +445,135 @@ struct Traj {
         return true;
     }
 
-    __device__ bool dm_sequential() const {
+    // Matching repair of the inner filter: every active row whose partner
+    // column left the residual gets a new one by one BFS augmentation (on
+    // lane 0, rows in index order; the rows that need one are found across
+    // the wave); false (in every lane) if the child has no perfect matching.
+    // `examined` counts on lane 0.
+    __device__ bool dm_match(uint64_t &examined) const {
+        const int l = lane_id();
         const auto queue = ws, parent = ws + n, vis = ws + 2 * n;
-        for (int32_t j = 0; j < n; ++j) {
+        for (int32_t j = l; j < n; j += kWave) {
             vis[j] = 0;
             if (active(n + j) && mate_c[j] >= 0 && !active(mate_c[j])) mate_c[j] = -1;
         }
+        wave_fence();
         int32_t stamp = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            if (!active(i)) continue;
-            const int32_t j = mate_r[i];
-            if (j >= 0 && active(n + j)) continue;
-            mate_r[i] = -1;
-            if (!augment_from(i, queue, parent, vis, ++stamp)) return false;
+        for (int32_t base = 0; base < n; base += kWave) {
+            const int32_t i = base + l;
+            bool need = false;
+            if (i < n && active(i)) {
+                const int32_t j = mate_r[i];
+                need = !(j >= 0 && active(n + j));
+            }
+            // an augmentation re-pairs only rows that already had a partner,
+            // so the rows found here still need one when their turn comes
+            uint64_t msk = ballot(need);
+            while (msk) {
+                const int32_t i0 = base + __ffsll((unsigned long long)msk) - 1;
+                msk &= msk - 1;
+                int ok = 1;
+                if (l == 0) {
+                    mate_r[i0] = -1;
+                    ok = augment_from(i0, queue, parent, vis, ++stamp, examined) ? 1 : 0;
+                }
+                ok = read_lane(ok, 0);
+                wave_fence();
+                if (!ok) return false;
+            }
         }
-        // Tarjan over active rows; comp[x] = id of x's component
+        return true;
+    }
+
+    // The contracted alternating digraph: node x = active row x with its
+    // partner column mate_r[x]; arcs x -> y for every other active row y of
+    // that column whose entry is not removed.
+    template <class F>
+    __device__ __forceinline__ void for_arcs(int32_t x, F &&f) const {
+        const int32_t jm = mate_r[x];
+        const int32_t end = M.col_ptr[jm + 1];
+        for (int32_t p = M.col_ptr[jm]; p < end; ++p) {
+            const int32_t y = M.row_idx[p];
+            if (y == x || !active(y) || removed(M.csc2csr[p])) continue;
+            f(y);
+        }
+    }
+
+    // Strongly connected components of that digraph across the wave, by
+    // rounds of max-label colouring: colour[y] becomes the largest live node
+    // id that reaches y (forward propagation to a fixed point); a node whose
+    // colour is its own id is a root, and the live nodes of its colour that
+    // reach it (a backward closure inside the colour class) form its
+    // component -- a path from such a node to the root stays in the class,
+    // since anything reaching a node on it reaches the root too.  Components
+    // found are removed and the next round colours what is left.
+    // comp[x] = the root of x's component.  false when kSccRounds rounds do
+    // not finish (long chains of components), leaving the work to Tarjan.
+    static constexpr int kSccRounds = 8;
+    __device__ bool scc_colouring(uint64_t &examined) const {
+        const int l = lane_id();
+        const auto colour = ws, vis = ws + n, comp = ws + 2 * n;
+        uint64_t ex = 0;
+        for (int32_t x = l; x < n; x += kWave) comp[x] = -1;
+        wave_fence();
+        bool done = false;
+        for (int round = 0; round < kSccRounds && !done; ++round) {
+            bool live_any = false;
+            for (int32_t x = l; x < n; x += kWave) {
+                const bool live = active(x) && comp[x] < 0;
+                colour[x] = live ? x : -1;
+                vis[x] = 0;
+                live_any = live_any || live;
+            }
+            wave_fence();
+            if (!ballot(live_any)) { done = true; break; }
+            for (;;) {  // forward: the largest id reaching each live node
+                bool ch = false;
+                for (int32_t x = l; x < n; x += kWave) {
+                    const int32_t cx = colour[x];
+                    if (cx < 0) continue;
+                    for_arcs(x, [&](int32_t y) {
+                        ++ex;
+                        if (colour[y] >= 0 && colour[y] < cx && atomicMax(&colour[y], cx) < cx) ch = true;
+                    });
+                }
+                wave_fence();
+                if (!ballot(ch)) break;
+            }
+            for (int32_t x = l; x < n; x += kWave)
+                if (colour[x] == x) vis[x] = 1;
+            wave_fence();
+            for (;;) {  // backward inside each colour class: the nodes reaching its root
+                bool ch = false;
+                for (int32_t x = l; x < n; x += kWave) {
+                    const int32_t cx = colour[x];
+                    if (cx < 0 || vis[x]) continue;
+                    bool reach = false;
+                    for_arcs(x, [&](int32_t y) {
+                        ++ex;
+                        if (!reach && vis[y] && colour[y] == cx) reach = true;
+                    });
+                    if (reach) { vis[x] = 1; ch = true; }
+                }
+                wave_fence();
+                if (!ballot(ch)) break;
+            }
+            for (int32_t x = l; x < n; x += kWave)
+                if (colour[x] >= 0 && vis[x]) comp[x] = colour[x];
+            wave_fence();
+        }
+        if (!done) {  // components may remain only if the last round left live nodes
+            bool left = false;
+            for (int32_t x = l; x < n; x += kWave) left = left || (active(x) && comp[x] < 0);
+            done = !ballot(left);
+        }
+        examined += wave_sum_u64(ex);
+        return done;
+    }
+
+    // The same components by an iterative Tarjan on lane 0 (comp[x] = the
+    // root of x's component); the fallback of scc_colouring.
+    __device__ void scc_tarjan(uint64_t &examined) const {
         const auto idx = ws, low = ws + n, comp = ws + 2 * n, stk = ws + 3 * n, fnode = ws + 4 * n,
                 fpos = ws + 5 * n;
         for (int32_t i = 0; i < n; ++i) { idx[i] = -1; comp[i] = -1; }
@@ -428,6 +592,7 @@ struct Traj {
                 bool descended = false;
                 while (fpos[top] < end) {
                     const int32_t p = fpos[top]++;
+                    ++examined;
                     const int32_t y = M.row_idx[p];
                     if (y == x || !active(y) || removed(M.csc2csr[p])) continue;
                     if (idx[y] < 0) {
@@ -450,7 +615,6 @@ struct Traj {
                 if (top >= 0 && low[x] < low[fnode[top]]) low[fnode[top]] = low[x];
             }
         }
-        return true;
     }
 
     // remove entries off the matching whose endpoints lie in different
@@ -501,7 +665,14 @@ struct Work {
     uint64_t sweeps = 0;      // full SK iterations
     uint64_t mlp_tiles = 0;   // 16-candidate tiles through the proposal network
     uint64_t scan_v = 0;      // adjacency entries read at the selected vertex
+    // device time by phase (wall-clock ticks of the wave, summed over its
+    // trajectories) and the entries the inner filter examined
+    uint64_t t_all = 0, t_sk = 0, t_dm = 0, t_loc = 0;
+    uint64_t dm_entries = 0;
 };
+
+// the device's constant-rate wall clock (ticks; the rate is a device attribute)
+__device__ __forceinline__ uint64_t wall_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 __device__ __forceinline__ uint64_t lemire_from(uint64_t x, uint64_t W, uint64_t seed, uint32_t k,
                                                 uint32_t b, uint32_t t) {
@@ -553,13 +724,39 @@ __device__ __forceinline__ int32_t wave_excl_scan_i32(int32_t x, int32_t &total)
     return (int32_t)incl - x;
 }
 
+// New scaling value of x for Eq. (local) from the pre-repair values: the
+// reciprocal of its child sum, or under a cap for a longer list the sampled
+// sum scaled by residual degree / sampled active count; unchanged when the
+// sum is zero (or nothing active was sampled).  `examined` counts entries.
+template <class TT>
+__device__ __forceinline__ float local_new_value(const TT &T, int32_t x, uint32_t k, int32_t t,
+                                                 uint64_t &examined) {
+    const float old = T.rec[x].s;
+    int32_t b0, e0;
+    T.list(x, b0, e0);
+    const int32_t L = e0 - b0, cap = T.a.local_cap;
+    if (cap > 0 && L > cap) {
+        int32_t cnt;
+        const float acc = T.sampled_sum(x, sample_offset(T.a.seed, k, T.a.b, (uint32_t)t, x, L), cap, cnt);
+        examined += (uint64_t)cap;
+        if (cnt > 0 && acc != 0.0f) {
+            const float est = acc * ((float)T.deg[x] / (float)cnt);
+            return 1.0f / est;
+        }
+        return old;
+    }
+    const float acc = T.residual_sum(x);
+    examined += (uint64_t)L;
+    return acc != 0.0f ? 1.0f / acc : old;
+}
+
 // Eq. (local).  rho_y: a column vertex of N_t(rho)\{gam} held by this lane
 // (or -1); gam_y: a row of N_t(gam)\{rho} (or -1).  R_loc / C_loc membership
 // is marked with stamps (step+1) << 6 | lane; when several lanes reach the
 // same vertex in one instruction the lane whose stamp survives keeps it.
 template <class TT>
-__device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, int32_t t,
-                                                   Work &work) {
+__device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, int32_t gam_y, uint32_t k,
+                                                   int32_t t, Work &work) {
     const int l = lane_id();
     const int32_t n = T.n;
     const int32_t mark = t + 1;
@@ -573,9 +770,20 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
         if (gam_y >= 0) { T.rec[gam_y].stamp = mine; T.loc_r[rank_below(mr)] = gam_y; }
         nr = __popcll(mr);
     }
-    int32_t gb = 0, gl = 0, rb = 0, rl = 0;
-    if (gam_y >= 0) { gb = T.M.row_ptr[gam_y]; gl = T.M.row_ptr[gam_y + 1] - gb; }
-    if (rho_y >= 0) { rb = T.M.col_ptr[rho_y - n]; rl = T.M.col_ptr[rho_y - n + 1] - rb; }
+    // examined entries per first-hop list: all of it, or cap sample positions
+    const int32_t cap = T.a.local_cap;
+    int32_t gb = 0, gl = 0, rb = 0, rl = 0, gL = 0, rL = 0;
+    uint32_t go = 0, ro = 0;
+    if (gam_y >= 0) {
+        gb = T.M.row_ptr[gam_y];
+        gL = gl = T.M.row_ptr[gam_y + 1] - gb;
+        if (cap > 0 && gL > cap) { gl = cap; go = sample_offset(T.a.seed, k, T.a.b, (uint32_t)t, gam_y, gL); }
+    }
+    if (rho_y >= 0) {
+        rb = T.M.col_ptr[rho_y - n];
+        rL = rl = T.M.col_ptr[rho_y - n + 1] - rb;
+        if (cap > 0 && rL > cap) { rl = cap; ro = sample_offset(T.a.seed, k, T.a.b, (uint32_t)t, rho_y, rL); }
+    }
     int32_t TG, TR;
     const int32_t og = wave_excl_scan_i32(gl, TG);
     const int32_t orr = wave_excl_scan_i32(rl, TR);
@@ -591,13 +799,23 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
         const int32_t fr = in_r ? f - TG : 0;
         const int or_o = owner_lane(fr, orr);
         const int32_t rb_o = __shfl(rb, or_o), or_v = __shfl(orr, or_o);
+        int32_t gL_o = 0, rL_o = 0;
+        uint32_t go_o = 0, ro_o = 0;
+        if (cap > 0) {
+            gL_o = __shfl(gL, og_o);
+            go_o = (uint32_t)__shfl((int32_t)go, og_o);
+            rL_o = __shfl(rL, or_o);
+            ro_o = (uint32_t)__shfl((int32_t)ro, or_o);
+        }
         int32_t tgt = -1, e = 0;
         if (in_g) {
-            const int32_t p = gb_o + (fg - og_v);
+            const int32_t i = fg - og_v;
+            const int32_t p = gb_o + (cap > 0 && gL_o > cap ? sample_pos(go_o, i, gL_o, cap) : i);
             tgt = n + T.M.col_idx[p];
             e = p;
         } else if (in_r) {
-            const int32_t p = rb_o + (fr - or_v);
+            const int32_t i = fr - or_v;
+            const int32_t p = rb_o + (cap > 0 && rL_o > cap ? sample_pos(ro_o, i, rL_o, cap) : i);
             tgt = T.M.row_idx[p];
             e = T.rem ? T.M.csc2csr[p] : 0;
         }
@@ -623,25 +841,13 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
         int32_t x = -1;
         float val = 0.0f;
         if (l < ne) x = l < nr ? T.loc_r[l] : n + T.loc_c[l - nr];
-        if (x >= 0) {
-            const float old = T.rec[x].s;
-            const float acc = T.residual_sum(x);
-            val = acc != 0.0f ? 1.0f / acc : old;
-            int32_t b0, e0;
-            T.list(x, b0, e0);
-            summed = e0 - b0;
-        }
+        if (x >= 0) val = local_new_value(T, x, k, t, summed);
         wave_fence();
         if (x >= 0) T.rec[x].s = val;
     } else {
         for (int32_t idx = l; idx < ne; idx += kWave) {
             const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
-            const float old = T.rec[x].s;
-            const float acc = T.residual_sum(x);
-            int32_t b0, e0;
-            T.list(x, b0, e0);
-            summed += e0 - b0;
-            T.new_v[idx] = acc != 0.0f ? 1.0f / acc : old;
+            T.new_v[idx] = local_new_value(T, x, k, t, summed);
         }
         wave_fence();
         for (int32_t idx = l; idx < ne; idx += kWave) {
@@ -658,8 +864,9 @@ __device__ __forceinline__ void local_repair_lanes(const TT &T, int32_t rho_y, i
 // the same sets and values, built one list at a time.
 template <class TT, class LP>
 __device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int32_t skip_rho,
-                                   LP gam_list, int32_t k_gam, int32_t skip_gam, int32_t t,
+                                   LP gam_list, int32_t k_gam, int32_t skip_gam, uint32_t k, int32_t t,
                                    Work &work) {
+    const int32_t cap = T.a.local_cap;
     const int l = lane_id();
     const int32_t n = T.n;
     const int32_t mark = t + 1;
@@ -687,12 +894,17 @@ __device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int3
         int32_t beg, end;
         T.list(x, beg, end);
         const bool row = x < n;
-        gathered += end - beg;
-        for (int32_t base = beg; base < end; base += kWave) {
-            const int32_t p = base + l;
+        const int32_t L = end - beg;
+        const bool smp = cap > 0 && L > cap;
+        const int32_t ne_x = smp ? cap : L;
+        const uint32_t o = smp ? sample_offset(T.a.seed, k, T.a.b, (uint32_t)t, x, L) : 0u;
+        gathered += ne_x;
+        for (int32_t base = 0; base < ne_x; base += kWave) {
+            const int32_t i = base + l;
+            const int32_t p = beg + (smp ? (i < ne_x ? sample_pos(o, i, L, cap) : 0) : i);
             bool take = false;
             int32_t y = 0;
-            if (p < end) {
+            if (i < ne_x) {
                 int32_t e; float bv;
                 T.entry(row, p, y, e, bv);
                 const Rec rc = T.rec[y];
@@ -720,12 +932,7 @@ __device__ void local_repair_lists(const TT &T, LP rho_list, int32_t k_rho, int3
     uint64_t summed = 0;
     for (int32_t idx = l; idx < ne; idx += kWave) {
         const int32_t x = idx < nr ? T.loc_r[idx] : n + T.loc_c[idx - nr];
-        const float old = T.rec[x].s;
-        const float acc = T.residual_sum(x);
-        int32_t b0, e0;
-        T.list(x, b0, e0);
-        summed += e0 - b0;
-        T.new_v[idx] = acc != 0.0f ? 1.0f / acc : old;
+        T.new_v[idx] = local_new_value(T, x, k, t, summed);
     }
     wave_fence();
     for (int32_t idx = l; idx < ne; idx += kWave) {
@@ -967,6 +1174,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
     const int l = lane_id();
     const int32_t n = a.A.n;
     const uint32_t k = (uint32_t)(a.first + q);
+    const uint64_t t_begin = wall_ticks();
     PE_G int32_t *path = a.path ? gptr(a.path) + (size_t)q * 2 * n : nullptr;
 
     // ---- initial state: template degrees, tree, scaling values, matching
@@ -974,7 +1182,12 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
         const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
         const auto dst = recast<uint4>(T.deg);
         for (int32_t i = l; i < a.n_leaf / 8; i += kWave) dst[i] = src[i];
-        for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = gptr(a.tree0)[i];
+        if (a.l0_state) {
+            for (int32_t i = l; i < a.tree.size[0]; i += kWave) T.lvl0[i] = gptr(a.tree0)[i];
+            for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = gptr(a.tree0)[a.tree_l1_src + i];
+        } else {
+            for (int32_t i = l; i < a.tree.total; i += kWave) T.tree[i] = gptr(a.tree0)[i];
+        }
         if (OWN) {
             for (int32_t x = l; x < 2 * n; x += kWave) {
                 float s = 1.0f;
@@ -1462,12 +1675,23 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             else if (a.dm_policy == kDmTrck && track < a.theta_tr) run_dm = true;
             if (run_dm) {
                 n_dm += 1;
-                int ok = 0;
-                if (l == 0) ok = T.dm_sequential() ? 1 : 0;
-                ok = read_lane(ok, 0);
-                wave_fence();
-                if (!ok) { alive = false; break; }
+                const uint64_t c0 = wall_ticks();
+                uint64_t dm_ex = 0;
+                const bool ok = T.dm_match(dm_ex);
+                if (!ok) {
+                    work.dm_entries += read_lane(dm_ex, 0);
+                    work.t_dm += wall_ticks() - c0;
+                    alive = false;
+                    break;
+                }
+                uint64_t scc_ex = 0;
+                if (!T.scc_colouring(scc_ex)) {
+                    if (l == 0) T.scc_tarjan(dm_ex);
+                    wave_fence();
+                }
+                work.dm_entries += read_lane(dm_ex, 0) + scc_ex;
                 T.dm_apply();
+                work.t_dm += wall_ticks() - c0;
                 track = 1.0;
                 ran_dm = true;
             }
@@ -1482,7 +1706,9 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 if (want > (double)a.K) want = (double)a.K;
                 nit = (int)want;
             }
+            const uint64_t c0 = wall_ticks();
             for (int it = 0; it < nit; ++it) T.sk_sweep();
+            work.t_sk += wall_ticks() - c0;
             n_sweeps += nit;
             work.sweeps += (uint64_t)nit;
         } else if (SK == kSkLocal || SK == kSkLearnedGated) {
@@ -1495,12 +1721,13 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                 fb = repair;
             }
             if (repair) {
+                const uint64_t c0 = wall_ticks();
                 // rho_list = N_t(rho)\{gam} (columns), gam_list = N_t(gam)\{rho} (rows)
                 if (fast_v && fast_u) {
                     const int32_t other_v = (cand && cy != u) ? cy : -1;
                     const int32_t other_u = take ? by : -1;
-                    if (v_row) local_repair_lanes(T, other_v, other_u, t, work);
-                    else local_repair_lanes(T, other_u, other_v, t, work);
+                    if (v_row) local_repair_lanes(T, other_v, other_u, k, t, work);
+                    else local_repair_lanes(T, other_u, other_v, k, t, work);
                 } else {
                     if (fast_v) {
                         const uint64_t msk = ballot(cand);
@@ -1511,9 +1738,10 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
                         if (take) T.lst_b[rank_below(msk)] = by;
                     }
                     wave_fence();
-                    if (v_row) local_repair_lists(T, T.lst_a, kc, u, T.lst_b, kb, -1, t, work);
-                    else local_repair_lists(T, T.lst_b, kb, -1, T.lst_a, kc, u, t, work);
+                    if (v_row) local_repair_lists(T, T.lst_a, kc, u, T.lst_b, kb, -1, k, t, work);
+                    else local_repair_lists(T, T.lst_b, kb, -1, T.lst_a, kc, u, k, t, work);
                 }
+                work.t_loc += wall_ticks() - c0;
                 n_local += 1;
             }
         }
@@ -1529,6 +1757,7 @@ __device__ __forceinline__ void run_trajectory(const PE_G TrajArgs &a, const Tra
             cn[0] = steps; cn[1] = n_dm; cn[2] = n_sweeps; cn[3] = n_local;
         }
     }
+    work.t_all += wall_ticks() - t_begin;
     wave_fence();
 }
 
@@ -1543,8 +1772,9 @@ struct BatchArgs {
     int32_t count;
     int64_t total;
     uint32_t *work_next;      // item counter (zeroed before launch)
-    unsigned long long *work_totals;  // [7]: scanned, decrements, local entries, local values, sweeps,
-                                      // tiles, scanned at the selected vertex
+    unsigned long long *work_totals;  // [12]: scanned, decrements, local entries, local values, sweeps,
+                                      // tiles, scanned at the selected vertex, wave ticks in trajectories,
+                                      // in full SK, in inner DM, in local repairs, DM entries examined
     char *hbm_state;          // base of the per-wave HBM slots, or nullptr if every matrix is LDS tier
     uint64_t hbm_stride;
     int32_t lds_tree_bytes;   // LDS bytes reserved per wave for min-tree nodes
@@ -1614,6 +1844,11 @@ traj_kernel(const BatchArgs *__restrict__ bp) {
         atomicAdd(B.work_totals + 4, (unsigned long long)work.sweeps);
         atomicAdd(B.work_totals + 5, (unsigned long long)work.mlp_tiles);
         atomicAdd(B.work_totals + 6, (unsigned long long)work.scan_v);
+        atomicAdd(B.work_totals + 7, (unsigned long long)work.t_all);
+        atomicAdd(B.work_totals + 8, (unsigned long long)work.t_sk);
+        atomicAdd(B.work_totals + 9, (unsigned long long)work.t_dm);
+        atomicAdd(B.work_totals + 10, (unsigned long long)work.t_loc);
+        atomicAdd(B.work_totals + 11, (unsigned long long)work.dm_entries);
     }
 }
 

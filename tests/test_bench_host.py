@@ -107,3 +107,13 @@ def test_byte_model_unit_costs():
     assert one(n_full_sk=1) == 18 * 30 + 16 * 10 and one(n_dm=1) == 27 * 30
     d = dict(z, n_entries_scanned_v=1)
     assert bench.algorithmic_bytes(d, 10, 30, scaled=False) == 0
+
+
+def test_time_to_target_is_the_checkpoint_after_the_last_violation():
+    """Sec. 4 "Metrics": the first logged checkpoint after the last one whose
+    relative error exceeds the target; the first one if none does; none if
+    the final one exceeds it."""
+    cps = [{"rel_error": e, "seconds": float(i)} for i, e in enumerate([0.5, 0.001, 0.02, 0.004, 0.003])]
+    assert bench.est_time(cps, 1e-2)["seconds"] == 3.0
+    assert bench.est_time(cps, 0.6)["seconds"] == 0.0
+    assert bench.est_time(cps, 1e-3) is None

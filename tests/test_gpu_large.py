@@ -92,3 +92,44 @@ def test_three_level_min_tree_power_law_learned():
     sched = P.preset("learned")
     model = R.quantize(R.init(32, scale=1.5))
     _check_sampled(M, sched, _osched(sched, model, 0.01), 4, 11, 2, [11, 12], model=model)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["learned", "local_nodm", "plain"])
+def test_tree_level0_in_state_slot_batch(name):
+    """A batch (one trajectory per wave) with a matrix of order 1.5e5, whose
+    min-tree keeps its lowest internal level in the trajectory's state slot
+    (above 2^18 leaves), beside a small LDS-tier matrix: sampled ids of both
+    against the oracle."""
+    import paper_2608_15390_amd as P
+    # a permuted band (no dead ends, so every sampled trajectory completes)
+    mats = [G.config_band(1, n=150_000)[0], G.planted_bernoulli(200, 0.04, 79, planted="random")]
+    sched = P.preset(name)
+    model = R.quantize(R.init(33, scale=1.5)) if name == "learned" else None
+    counts = [6, 40]
+    print(f"[gpu] level-0-in-state batch n={[M.n for M in mats]} sched={name}", flush=True)
+    bt = P.PermEstBatch(mats)
+    if model is not None:
+        bt.set_model(torch.as_tensor(model, dtype=torch.float32, device="cuda"), 0.01)
+    out = bt.run(counts, 9, sched, want_hash=True)
+    torch.cuda.synchronize()
+    lw, al = out["logw"].cpu().numpy(), out["alive"].cpu().numpy()
+    ph = out["path_hash"].cpu().numpy().view(np.uint64)
+    off = out["offsets"]
+    osch = _osched(sched, model, 0.01)
+    bt.close()
+    for b, M in enumerate(mats):
+        A = O.OMatrix(M)
+        picks = [0, counts[b] - 1] if b == 0 else list(range(counts[b]))
+        o = O.run(A, osch, seed=9, first=0, count=counts[b], b=b, nthreads=8) if b == 1 else None
+        for k in picks:
+            if b == 0:
+                ok = O.run(A, osch, seed=9, first=k, count=1, b=b)
+                ref = {key: v[0] for key, v in ok.items()}
+            else:
+                ref = {key: v[k] for key, v in o.items()}
+            i = off[b] + k
+            assert al[i] == ref["alive"], (b, k)
+            assert ph[i] == ref["path_hash"], (b, k)
+            if ref["alive"]:
+                assert lw[i] == pytest.approx(ref["logw"], rel=1e-12, abs=0), (b, k)

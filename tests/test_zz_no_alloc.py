@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 
 STAT_KEYS = ("log_estimate", "p_match", "rel_spread", "rse", "ess", "var_logw", "max_logw", "n_traj", "n_alive",
              "n_dm", "n_full_sk", "n_local_sk", "n_steps", "n_entries_scanned", "n_decrements",
-             "n_local_entries", "n_local_values", "n_mlp_tiles")
+             "n_local_entries", "n_local_values")
 
 
 def _same(a, b, what):
@@ -26,6 +26,9 @@ def _same(a, b, what):
     for k in STAT_KEYS:
         x, y = a["result"][k], b["result"][k]
         assert x == y or (x != x and y != y), (what, k, x, y)
+    # network tiles depend on which trajectories share a wave (four per
+    # wave share 16-record tiles), so a smaller grid may pack them otherwise
+    assert (a["result"]["n_mlp_tiles"] > 0) == (b["result"]["n_mlp_tiles"] > 0), what
 
 
 def _pair(est, first, count, seed, sched, **want):

@@ -313,32 +313,22 @@ struct Traj {
     // ------------------------------------------------------------ SK
     // one full iteration over the residual: columns with the old r, then
     // rows with the new c; sequential binary32 sums in list order
+    // One SK iteration on the residual: every active column from the old
+    // rows, then every active row from the new columns (sums in list order,
+    // eight entries' loads in flight at a time; a matched vertex has a
+    // negative scale).
     __device__ void sk_sweep() const {
         const int l = lane_id();
         for (int32_t j = l; j < n; j += kWave) {
-            if (!active(n + j)) continue;
-            float acc = 0.0f;
-            for (int32_t p = M.col_ptr[j]; p < M.col_ptr[j + 1]; ++p) {
-                const int32_t i = M.row_idx[p];
-                if (!active(i)) continue;
-                if (DM && removed(M.csc2csr[p])) continue;
-                const float bv = WT ? M.val_csc[p] : 1.0f;
-                const float prod = bv * rec[i].s;
-                acc = acc + prod;
-            }
-            if (acc != 0.0f) rec[n + j].s = 1.0f / acc;
+            const int32_t x = n + j;
+            if (!(rec[x].s >= 0.0f)) continue;
+            const float acc = residual_sum(x);
+            if (acc != 0.0f) rec[x].s = 1.0f / acc;
         }
         wave_fence();
         for (int32_t i = l; i < n; i += kWave) {
-            if (!active(i)) continue;
-            float acc = 0.0f;
-            for (int32_t e = M.row_ptr[i]; e < M.row_ptr[i + 1]; ++e) {
-                const int32_t j = M.col_idx[e];
-                if (!active(n + j) || removed(e)) continue;
-                const float bv = WT ? M.val[e] : 1.0f;
-                const float prod = bv * rec[n + j].s;
-                acc = acc + prod;
-            }
+            if (!(rec[i].s >= 0.0f)) continue;
+            const float acc = residual_sum(i);
             if (acc != 0.0f) rec[i].s = 1.0f / acc;
         }
         wave_fence();

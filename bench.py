@@ -258,21 +258,30 @@ def bootstrap_ci(vals, reps=2000, seed=0):
     return [float(np.percentile(means, 2.5)), float(np.percentile(means, 97.5))]
 
 
-def ladder(params, plain_sched, learned_sched, seeds):
+def ladder(params, plain_sched, learned_sched, seeds, gated_sched=None):
     """The same comparison on smaller matrices of the same family, where the
-    effective sample size does not collapse, replicated over run seeds."""
+    effective sample size does not collapse, replicated over run seeds; with
+    `gated_sched`, the learned proposal with its gated fallback (local repair
+    and the scaled proposal after a surprising step) runs the same seeds."""
     import paper_2608_15390_amd as P
     from paper_2608_15390_amd import inputs as G
     from paper_2608_15390_amd import learned as LR
 
+    methods = [("learned", learned_sched), ("plain", plain_sched)]
+    if gated_sched is not None:
+        methods.append(("gated", gated_sched))
     rows = []
     for n, cnt in ((1000, 100_000), (10_000, 20_000)):
         M = G.planted_uniform(n, 7 * n, 5)
         est = P.PermEst(M)
         est.set_model(params, LR.MIX_ALPHA)
-        row = {"n": n, "n_traj": cnt, "seeds": list(seeds), "learned": [], "plain": [], "ratio": []}
+        row = {"n": n, "n_traj": cnt, "seeds": list(seeds), "ratio": []}
+        for name, _ in methods:
+            row[name] = []
+        if gated_sched is not None:
+            row["ratio_gated"] = []
         for s in seeds:
-            for name, sch in (("learned", learned_sched), ("plain", plain_sched)):
+            for name, sch in methods:
                 est.run(0, 64, s, sch, want_logw=False, want_alive=False)
                 out, secs = timed_run(est, 0, cnt, s, sch, want=True)
                 rec = summary(out["result"], secs)
@@ -280,12 +289,18 @@ def ladder(params, plain_sched, learned_sched, seeds):
                                                  out["alive"].cpu().numpy().astype(bool), secs)
                 row[name].append(rec)
             row["ratio"].append(row["learned"][-1]["ess_per_s"] / row["plain"][-1]["ess_per_s"])
+            if gated_sched is not None:
+                row["ratio_gated"].append(row["gated"][-1]["ess_per_s"] / row["plain"][-1]["ess_per_s"])
         print(f"[bench]   ladder n={n}: ratios {[round(r, 3) for r in row['ratio']]}", file=sys.stderr, flush=True)
         row["ratio_mean"] = float(np.mean(row["ratio"]))
         row["ratio_ci95"] = bootstrap_ci(row["ratio"])
-        for name in ("learned", "plain"):
+        if gated_sched is not None:
+            row["ratio_gated_mean"] = float(np.mean(row["ratio_gated"]))
+            row["ratio_gated_ci95"] = bootstrap_ci(row["ratio_gated"])
+        for name, _ in methods:
             row[f"{name}_ess_per_s_mean"] = float(np.mean([r["ess_per_s"] for r in row[name]]))
             row[f"{name}_var_logw_mean"] = float(np.mean([r["var_logw"] for r in row[name]]))
+            row[f"{name}_traj_per_s_mean"] = float(np.mean([r["traj_per_s"] for r in row[name]]))
         rows.append(row)
         est.close()
     return rows
@@ -572,18 +587,22 @@ def blocks_main(args) -> int:
 
 
 CONSENSUS_SETS = {
+    # the band of mean degree 8 at n = 1e3, whose permanent is known exactly
+    # (stored reference): the diagnostics can be checked against the truth
+    "band_n1e3": {"n": 1000, "variants": VARIANTS, "n_traj": 4096},
     # n = 1e3, the large workload's family (avg degree 8): the five variants of Sec. 4
-    "n1e3": {"n": 1000, "variants": VARIANTS, "n_traj": 16384},
+    "n1e3": {"n": 1000, "variants": VARIANTS, "n_traj": 4096},
     # the large workload itself (n = 1e5): the methods that run there
-    "n1e5": {"n": 100_000, "variants": ("local_nodm", "learned", "learned_gated"), "n_traj": 4000},
+    "n1e5": {"n": 100_000, "variants": ("local_nodm", "learned", "learned_gated"), "n_traj": 2000},
 }
 
 
 def consensus_main(args) -> int:
-    """Multi-seed consensus diagnostics (Sec. 4.4) for matrices whose
-    permanent is not known: V variants x 5 run seeds on one matrix of the
-    large workload's family at n = 1e3 (the five variants of Sec. 4) and on
-    the n = 1e5 matrix itself (local repair, learned proposal with and
+    """Multi-seed consensus diagnostics (Sec. 4.4): V variants x 5 run seeds
+    on a band matrix of mean degree 8 at n = 1e3 whose permanent is known
+    (so the diagnostics can be checked against the truth), on one matrix of
+    the large workload's family at n = 1e3 (the five variants of Sec. 4) and
+    on the n = 1e5 matrix itself (local repair, learned proposal with and
     without its gated fallback), each run a fixed number of trajectories;
     the library's perm_est_consensus gives the equal-variant consensus, its
     relative half-width, the variant ratio, D_max against the Bonferroni
@@ -597,7 +616,15 @@ def consensus_main(args) -> int:
     params = None
     out = {}
     for tag, cfg in CONSENSUS_SETS.items():
-        M = G.planted_uniform(cfg["n"], 7 * cfg["n"], 5) if cfg["n"] < 100_000 else G.config_large(1)
+        exact = None
+        if tag.startswith("band"):
+            M, _ = G.config_band(1, n=cfg["n"])
+            with open(os.path.join(ROOT, "tests", "golden", "band_n1e3_hw4.json")) as f:
+                exact = json.load(f)["log_permanent"]
+        elif cfg["n"] < 100_000:
+            M = G.planted_uniform(cfg["n"], 7 * cfg["n"], 5)
+        else:
+            M = G.config_large(1)
         if any(v.startswith("learned") for v in cfg["variants"]) and params is None:
             params, _ = LR.train_proposal(G.config_train(1), epochs=args.train_epochs, seed=args.seed)
         est = P.PermEst(M, device=0)
@@ -622,12 +649,17 @@ def consensus_main(args) -> int:
         c["n"] = M.n
         c["n_traj_per_run"] = cfg["n_traj"]
         c["seconds_per_variant"] = secs
+        if exact is not None:
+            # the truth, for this check only: where it falls against the consensus interval
+            c["exact_log_permanent"] = exact
+            c["consensus_rel_error"] = math.expm1(c["log_p_con"] - exact)
+            c["truth_within_half_width"] = abs(c["consensus_rel_error"]) <= c["rel_half_width"]
         c["runs"] = [[{k: r[k] for k in ("log_estimate", "rse", "ess", "p_match", "n_alive")} for r in row]
                      for row in runs]
         out[tag] = c
     line = {
         "metric": "multi-seed consensus: relative 95% half-width of the equal-variant consensus",
-        "value": out["n1e3"]["rel_half_width"], "unit": "relative", "n_gpus": 1,
+        "value": out["band_n1e3"]["rel_half_width"], "unit": "relative (band n = 1e3)", "n_gpus": 1,
         "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator)",
         "config": {"workload": "consensus", "seeds": args.consensus_seeds}, "consensus": out,
     }
@@ -936,7 +968,8 @@ def main() -> int:
         }
         if not args.no_ladder:
             print("[bench] ladder n=1e3, 1e4", file=sys.stderr, flush=True)
-            cmp["ladder"] = ladder(params, plain_sched, learned_sched, [args.seed + i for i in range(args.ladder_seeds)])
+            cmp["ladder"] = ladder(params, plain_sched, learned_sched, [args.seed + i for i in range(args.ladder_seeds)],
+                                   gated_sched=P.preset("learned_gated"))
         if not args.no_band:
             print("[bench] band matrices n=1e3, 1e4, 1e5 (exact permanent known)", file=sys.stderr, flush=True)
             cmp["band"] = band_study(params, plain_sched, learned_sched, args.seed, args.band_traj)

@@ -860,10 +860,15 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     // a block's LDS, the matrix runs one trajectory per wave instead)
     const bool rows_ok = count == 1 && !rec && !dm && sched->vertex_rule == PE_VR_MD && hbm_cap > 0 &&
                          !parts[0].path && !(h->opt_flags & PE_FLAG_WAVE_PER_TRAJECTORY);
+    // Rows only while four of their waves (sixteen trajectories) fit a CU's
+    // LDS: a wave of rows holds four trees, so at large n the rows would
+    // run fewer trajectories per CU than whole waves, whose lowest tree
+    // level then moves to the state slot (below).
+    const size_t lds4 = std::min(kLdsBlock, kLdsCU);
     const bool rows_learned = rows_ok && learned && !gated &&
-                              block_fixed + 4 * tree_bytes + (size_t)kRowNetScratchBytes <= kLdsBlock;
+                              block_fixed + 4 * (4 * tree_bytes + (size_t)kRowNetScratchBytes) <= lds4;
     const bool rows = rows_learned || (rows_ok && sched->sk_policy == PE_SK_NONE &&
-                                       block_fixed + 4 * tree_bytes + (size_t)lds_cap <= kLdsBlock);
+                                       block_fixed + 4 * (4 * tree_bytes + (size_t)lds_cap) <= lds4);
     const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt) : rows_kernel_fn(wt);
     const int tpw = rows ? 4 : 1;  // trajectories per wave
     // One trajectory per wave: a large matrix keeps the lowest internal level

@@ -477,16 +477,35 @@ struct Traj {
 
     // The contracted alternating digraph: node x = active row x with its
     // partner column mate_r[x]; arcs x -> y for every other active row y of
-    // that column whose entry is not removed.
-    template <class F>
-    __device__ __forceinline__ void for_arcs(int32_t x, F &&f) const {
+    // that column whose entry is not removed.  scan_arcs visits the arcs of x
+    // eight entries at a time, with the loads of each batch in flight
+    // together (rows, then their colours, visit marks and edge ids, then the
+    // removed bits): f(y, colour[y], vis[y]) for every arc whose head is
+    // live (colour >= 0: inactive rows and rows already in a component have
+    // colour -1).  Returns the entries examined.
+    template <bool NEED_VIS, class F>
+    __device__ __forceinline__ uint32_t scan_arcs(int32_t x, as_ptr<AS, int32_t> colour, as_ptr<AS, int32_t> vis,
+                                                  F &&f) const {
         const int32_t jm = mate_r[x];
-        const int32_t end = M.col_ptr[jm + 1];
-        for (int32_t p = M.col_ptr[jm]; p < end; ++p) {
-            const int32_t y = M.row_idx[p];
-            if (y == x || !active(y) || removed(M.csc2csr[p])) continue;
-            f(y);
+        const int32_t beg = M.col_ptr[jm], end = M.col_ptr[jm + 1];
+        for (int32_t p0 = beg; p0 < end; p0 += 8) {
+            int32_t y[8], cy[8], vy[8], e[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) y[i] = M.row_idx[p0 + i < end ? p0 + i : end - 1];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                cy[i] = colour[y[i]];
+                vy[i] = NEED_VIS ? vis[y[i]] : 0;
+                e[i] = M.csc2csr[p0 + i < end ? p0 + i : end - 1];
+            }
+            bool rm[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) rm[i] = removed(e[i]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (p0 + i < end && y[i] != x && cy[i] >= 0 && !rm[i]) f(y[i], cy[i], vy[i]);
         }
+        return (uint32_t)(end - beg);
     }
 
     // Strongly connected components of that digraph across the wave, by
@@ -522,9 +541,8 @@ struct Traj {
                 for (int32_t x = l; x < n; x += kWave) {
                     const int32_t cx = colour[x];
                     if (cx < 0) continue;
-                    for_arcs(x, [&](int32_t y) {
-                        ++ex;
-                        if (colour[y] >= 0 && colour[y] < cx && atomicMax(&colour[y], cx) < cx) ch = true;
+                    ex += scan_arcs<false>(x, colour, vis, [&](int32_t y, int32_t cy, int32_t) {
+                        if (cy < cx && atomicMax(&colour[y], cx) < cx) ch = true;
                     });
                 }
                 wave_fence();
@@ -539,9 +557,8 @@ struct Traj {
                     const int32_t cx = colour[x];
                     if (cx < 0 || vis[x]) continue;
                     bool reach = false;
-                    for_arcs(x, [&](int32_t y) {
-                        ++ex;
-                        if (!reach && vis[y] && colour[y] == cx) reach = true;
+                    ex += scan_arcs<true>(x, colour, vis, [&](int32_t, int32_t cy, int32_t vy) {
+                        if (vy && cy == cx) reach = true;
                     });
                     if (reach) { vis[x] = 1; ch = true; }
                 }
@@ -612,34 +629,50 @@ struct Traj {
     __device__ void dm_apply() const {
         const int l = lane_id();
         const auto comp = ws + 2 * n;
-        const int32_t words = (a.A.m + 31) / 32;
-        for (int32_t w = l; w < words; w += kWave) {
-            uint32_t bits = rem[w];
-            for (int32_t b = 0; b < 32; ++b) {
-                const int32_t e = 32 * w + b;
-                if (e >= a.A.m || ((bits >> b) & 1u)) continue;
+        // one edge per lane: 64 edges = two bitmap words per pass, the cut
+        // bits gathered by a ballot and or-ed in by lanes 0 and 32
+        for (int32_t base = 0; base < a.A.m; base += kWave) {
+            const int32_t e = base + l;
+            bool cut = false;
+            if (e < a.A.m && !removed(e)) {
                 const int32_t i = M.edge_row[e];
                 const int32_t j = M.col_idx[e];
-                if (!active(i) || !active(n + j) || mate_r[i] == j) continue;
-                if (comp[i] != comp[mate_c[j]]) bits |= 1u << b;
+                if (active(i) && active(n + j) && mate_r[i] != j) cut = comp[i] != comp[mate_c[j]];
             }
-            rem[w] = bits;
+            const uint64_t b = ballot(cut);
+            if (l == 0 && (uint32_t)b) rem[base >> 5] |= (uint32_t)b;
+            if (l == 32 && (b >> 32)) rem[(base >> 5) + 1] |= (uint32_t)(b >> 32);
         }
         wave_fence();
-        for (int32_t x = l; x < 2 * n; x += kWave) {
-            if (!active(x)) continue;
-            int32_t beg, end, c = 0;
-            list(x, beg, end);
-            const bool row = x < n;
-            for (int32_t p = beg; p < end; ++p) {
-                int32_t y, e; float bv;
-                entry(row, p, y, e, bv);
-                if (active(y) && !removed(e)) ++c;
-            }
-            deg[x] = (uint16_t)c;
-        }
+        for (int32_t x = l; x < 2 * n; x += kWave)
+            if (active(x)) deg[x] = (uint16_t)residual_count(x);
         wave_fence();
         tree_rebuild();
+    }
+
+    // number of residual neighbours of x (active, entry not removed), with
+    // eight entries' loads in flight at a time
+    __device__ int32_t residual_count(int32_t x) const {
+        const bool row = x < n;
+        int32_t beg, end;
+        list(x, beg, end);
+        int32_t c = 0;
+        for (int32_t p0 = beg; p0 < end; p0 += 8) {
+            int32_t y[8], e[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t p = p0 + i < end ? p0 + i : end - 1;
+                y[i] = row ? n + M.col_idx[p] : M.row_idx[p];
+                e[i] = row ? p : (DM ? M.csc2csr[p] : 0);
+            }
+            uint32_t d[8];
+            bool rm[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) { d[i] = deg[y[i]]; rm[i] = removed(e[i]); }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c += (p0 + i < end && d[i] != kRetired && !rm[i]) ? 1 : 0;
+        }
+        return c;
     }
 };
 

@@ -5,9 +5,13 @@
   recomputed one by one by the oracle.
 * One matrix of order 6e5, where the min-tree over 2n degree leaves needs
   three levels (more than 64 x 64 groups of 256 leaves): the plain
-  estimator (its default four-trajectories-per-wave launch and whole
-  waves), the local repair and the learned proposal, on a planted uniform
-  matrix and on a power-law one (degrees up to 200).
+  estimator (default launch and forced whole waves), the local repair and
+  the learned proposal, on a planted uniform matrix and on a power-law one
+  (degrees up to 200).  At this order four trees per wave no longer fit
+  four waves in a CU's LDS, so every launch takes whole waves with the
+  tree's lowest level in the state slot.
+* A batch holding an order-1.5e5 matrix (level 0 in the state slot) beside
+  a small LDS-tier one.
 
 Paths, alive flags, counters and path hashes compare bit for bit, ln X to
 1e-12 relative (the oracle's stated FP64 agreement)."""

@@ -18,7 +18,8 @@ ln X) and T the wall time of the K timed steps.  The plain scaled method
 (one local SK repair per step, no inner filter) then runs the same ids in
 the same chunks, timed the same way, and the ratio of the two is reported.
 Launches run up to --streams at a time (one handle and HIP stream each,
-default 4), so that 5000-trajectory launches still fill the chip.
+default 3: one per hardware queue the runtime gives a process beside its
+default stream), so that 5000-trajectory launches still fill the chip.
 At n = 1e5 both ESS values collapse towards 1 (see "degenerate"), so the
 same comparison also runs at n = 1e3 and 1e4 over five run seeds (mean
 ratio, bootstrap interval, time to RSE 0.1 and 0.01), and on band matrices
@@ -401,13 +402,15 @@ def batch_main(args) -> int:
           f"{n_traj} trajectories each, {sched_name}", file=sys.stderr, flush=True)
     # set-up: preprocessing, autotuning and graph capture happen on the first runs
     for w in range(max(1, args.warmup)):
-        bt.run(n_traj, args.seed + 1000 + w, sched, want_logw=False, want_alive=False, autotune=True, graph=True)
+        bt.run(n_traj, args.seed + 1000 + w, sched, want_logw=False, want_alive=False, autotune=True,
+               graph=not args.no_graph)
         print(f"[bench]   warmup {w + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        out = bt.run(n_traj, args.seed + k, sched, want_logw=False, want_alive=False, autotune=True, graph=True)
+        out = bt.run(n_traj, args.seed + k, sched, want_logw=False, want_alive=False, autotune=True,
+                     graph=not args.no_graph)
         results.append(out["results"])
         print(f"[bench]   step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -446,7 +449,7 @@ def batch_main(args) -> int:
         "dtype": "f64", "data": "synthetic (seeded generator)",
         "config": {"workload": wname, "matrices": len(mats), "n_traj_per_matrix": n_traj,
                    "n_total": int(sum(M.n for M in mats)), "nnz_total": int(sum(M.nnz for M in mats)),
-                   "schedule": sched_name, "parallelism": "1 GPU", "autotune": True, "graph": True},
+                   "schedule": sched_name, "parallelism": "1 GPU", "autotune": True, "graph": not args.no_graph},
         "estimate": {"trajectories_per_s": len(mats) * n_traj * args.steps / secs,
                      "steps_per_s": steps / secs, "ess_sum": ess,
                      "p_match_mean": float(np.mean([r["p_match"] for r in results[0]])),
@@ -779,12 +782,13 @@ def main() -> int:
     ap.add_argument("--consensus-seeds", type=int, default=5, help="run seeds per variant (consensus)")
     ap.add_argument("--hub-n", type=int, default=20_000, help="order of the power-law matrix (hubs)")
     ap.add_argument("--batch-schedule", default="adaptive_threshold")
+    ap.add_argument("--no-graph", action="store_true", help="batch: eager launches instead of graph replay")
     ap.add_argument("--method", default="learned", choices=["learned", "plain"],
                     help="method whose job is timed as `value`")
     ap.add_argument("--plain-schedule", default="local_nodm")
     ap.add_argument("--learned-schedule", default="learned")
     ap.add_argument("--n-traj", type=int, default=None, help="trajectories of the whole job")
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=3,
                     help="launches in flight together (one handle and HIP stream each)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--train-epochs", type=int, default=4)

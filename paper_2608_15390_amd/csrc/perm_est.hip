@@ -865,8 +865,50 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     // run fewer trajectories per CU than whole waves, whose lowest tree
     // level then moves to the state slot (below).
     const size_t lds4 = std::min(kLdsBlock, kLdsCU);
-    const bool rows_learned = rows_ok && learned && !gated &&
-                              block_fixed + 4 * (4 * tree_bytes + (size_t)kRowNetScratchBytes) <= lds4;
+    // the tree's lowest level, moved to a trajectory's state slot: LDS then
+    // holds only the levels above it (offsets from 0)
+    auto relocate_l0 = [&](size_t b) -> int {
+        TrajArgs &a = h->args_host[b];
+        const TreeLayout &full = prep[b]->tree;
+        const uint64_t at = (mat_bytes[b] + 255) / 256 * 256;
+        const uint64_t end = (at + 4ull * full.size[0] + 255) / 256 * 256;
+        if (end >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
+        a.st.lvl0 = (uint32_t)at;
+        a.st.bytes = (uint32_t)end;
+        mat_bytes[b] = end;
+        hbm_cap = std::max<uint64_t>(hbm_cap, end);
+        a.l0_state = 1;
+        a.tree_l1_src = full.off[1];
+        TreeLayout up = full;
+        int32_t o = 0;
+        up.off[0] = 0;
+        for (int k = 1; k < full.levels; ++k) { up.off[k] = o; o += full.size[k]; }
+        up.total = (o + 3) / 4 * 4;
+        a.tree = up;
+        return PE_OK;
+    };
+    // learned rows: four trees per wave would cap the CU at fewer waves than
+    // its registers allow (84 VGPRs: 24 waves), so the lowest tree level goes
+    // to the row's state slot (one more dependent load per selection, three
+    // times the waves in flight)
+    const bool learned_rows_cand = rows_ok && learned && !gated;
+    bool l0_rows = false;
+    size_t row_tree_bytes = tree_bytes;
+    if (learned_rows_cand && prep[0]->tree.levels >= 2 &&
+        block_fixed + 24 * (4 * tree_bytes + (size_t)kRowNetScratchBytes) > kLdsCU) {
+        const TreeLayout &full = prep[0]->tree;
+        int32_t up = 0;
+        for (int k = 1; k < full.levels; ++k) up += full.size[k];
+        row_tree_bytes = ((size_t)((up + 3) / 4 * 4) * 4 + 15) / 16 * 16;
+        l0_rows = true;
+    }
+    const bool rows_learned = learned_rows_cand &&
+                              block_fixed + 4 * (4 * row_tree_bytes + (size_t)kRowNetScratchBytes) <= lds4;
+    if (rows_learned && l0_rows) {
+        if ((rc = relocate_l0(0))) return rc;
+        tree_bytes = row_tree_bytes;
+        B.lds_tree_bytes = (int32_t)tree_bytes;
+    }
     const bool rows = rows_learned || (rows_ok && sched->sk_policy == PE_SK_NONE &&
                                        block_fixed + 4 * (4 * tree_bytes + (size_t)lds_cap) <= lds4);
     const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt) : rows_kernel_fn(wt);
@@ -880,23 +922,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         for (size_t b = 0; b < count; ++b) {
             TrajArgs &a = h->args_host[b];
             const TreeLayout &full = prep[b]->tree;
-            if (!a.lds_tier && full.levels >= 2 && (size_t)full.size[0] * 4 > kTreeLevel0LdsMax) {
-                const uint64_t at = (mat_bytes[b] + 255) / 256 * 256;
-                const uint64_t end = (at + 4ull * full.size[0] + 255) / 256 * 256;
-                if (end >= (1ull << 32)) return fail(PE_ENOTSUP, "per-trajectory state exceeds 4 GiB");
-                a.st.lvl0 = (uint32_t)at;
-                a.st.bytes = (uint32_t)end;
-                mat_bytes[b] = end;
-                hbm_cap = std::max<uint64_t>(hbm_cap, end);
-                a.l0_state = 1;
-                a.tree_l1_src = full.off[1];
-                TreeLayout up = full;  // LDS holds levels 1.. only
-                int32_t o = 0;
-                up.off[0] = 0;
-                for (int k = 1; k < full.levels; ++k) { up.off[k] = o; o += full.size[k]; }
-                up.total = (o + 3) / 4 * 4;
-                a.tree = up;
-            }
+            if (!a.lds_tier && full.levels >= 2 && (size_t)full.size[0] * 4 > kTreeLevel0LdsMax)
+                if ((rc = relocate_l0(b))) return rc;
             lds_total = std::max(lds_total, a.tree.total);
         }
         tree_bytes = ((size_t)lds_total * 4 + 15) / 16 * 16;

@@ -113,8 +113,9 @@ struct RowTraj {
     PE_G int32_t *lst_a, *lst_b;
     uint32_t *tree;
     int32_t n;
+    uint32_t *lvl0;  // the tree's lowest internal level: in LDS, or in the state slot
 
-    __device__ uint32_t *level(int k) const { return tree + a.tree.off[k]; }
+    __device__ uint32_t *level(int k) const { return k == 0 ? lvl0 : tree + a.tree.off[k]; }
     __device__ void list(int32_t x, int32_t &b, int32_t &e) const {
         if (x < n) { b = M.row_ptr[x]; e = M.row_ptr[x + 1]; }
         else { b = M.col_ptr[x - n]; e = M.col_ptr[x - n + 1]; }
@@ -228,9 +229,9 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
     char *mine = smem + (size_t)wave * 4 * (size_t)B.lds_tree_bytes;
     PE_G char *state = gptr(B.hbm_state) + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
     const auto &L = a.st;
+    uint32_t *tree_row = reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
     const RowTraj T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
-                    recast<int32_t>(state + L.lst_b),
-                    reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes), n};
+                    recast<int32_t>(state + L.lst_b), tree_row, n, tree_row + a.tree.off[0]};
     Work work;
     // per-row trajectory registers (uniform within the row)
     int phase = 0;  // 0 claim, 1 running, 2 no more work

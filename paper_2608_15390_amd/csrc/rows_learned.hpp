@@ -195,9 +195,12 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
     RowNetScratch *scr = reinterpret_cast<RowNetScratch *>(mine + 4 * (size_t)B.lds_tree_bytes);
     PE_G char *state = gptr(B.hbm_state) + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
     const auto &L = a.st;
+    // the tree's lowest level lives in the row's state slot when the launch
+    // moved it there (LDS then holds the levels above, offsets from 0)
+    uint32_t *tree_row = reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
+    uint32_t *lvl0 = a.l0_state ? reinterpret_cast<uint32_t *>((char *)state + L.lvl0) : tree_row + a.tree.off[0];
     const RowTraj T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
-                    recast<int32_t>(state + L.lst_b),
-                    reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes), n};
+                    recast<int32_t>(state + L.lst_b), tree_row, n, lvl0};
     const double alpha = a.mix_alpha;
     const ArgTree AT{T};
     Work work;
@@ -233,7 +236,13 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
                 const auto dst = recast<uint4>(T.deg);
                 for (int32_t i = rl; i < a.n_leaf / 8; i += kRowLanes) dst[i] = src[i];
-                for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = gptr(a.tree0a)[i];
+                if (a.l0_state) {
+                    for (int32_t i = rl; i < a.tree.size[0]; i += kRowLanes) T.lvl0[i] = gptr(a.tree0a)[i];
+                    for (int32_t i = rl; i < a.tree.total; i += kRowLanes)
+                        T.tree[i] = gptr(a.tree0a)[a.tree_l1_src + i];
+                } else {
+                    for (int32_t i = rl; i < a.tree.total; i += kRowLanes) T.tree[i] = gptr(a.tree0a)[i];
+                }
                 wave_fence();
             }
         }

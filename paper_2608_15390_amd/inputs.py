@@ -379,6 +379,22 @@ def with_weights(M: SparseMatrix, seed: int, lo: float = 1.0, hi: float = 1.5) -
     return SparseMatrix(M.n, M.row_ptr, M.col_idx, M.col_ptr, M.row_idx, v, dict(M.meta, weighted=True))
 
 
+# ------------------------------------------------------- network parameters
+def network_params(seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Random initial parameters of the 8-64-64-1 proposal network (float64,
+    packed W1[8][64], b1[64], W2[64][64], b2[64], w3[64], b3): He-normal
+    weights scaled by `scale`, inputs 6 and 7 (unused features) zero, biases
+    0.05 and 0.  A seeded generator like the matrices above, shared by the
+    trainer's start and the tests."""
+    IN, H = 8, 64
+    g = np.random.default_rng(seed)
+    W1 = g.normal(0.0, scale * np.sqrt(2.0 / 6), (IN, H))
+    W1[6:, :] = 0.0
+    W2 = g.normal(0.0, scale * np.sqrt(2.0 / H), (H, H))
+    w3 = g.normal(0.0, scale * np.sqrt(1.0 / H), H)
+    return np.concatenate([W1.ravel(), np.full(H, 0.05), W2.ravel(), np.full(H, 0.05), w3, np.zeros(1)])
+
+
 # ------------------------------------------------------------ workloads
 def config_small(seed: int = 1) -> SparseMatrix:
     """n = 20: identity plus Bernoulli(0.2) off-diagonal entries."""

@@ -13,20 +13,12 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 from . import MLP_NPARAM, PermEstBatch, ProposalNet, preset
-from .inputs import SparseMatrix
-
-IN, H = 8, 64
+from .inputs import SparseMatrix, network_params
 
 
 def init_params(seed: int = 0, scale: float = 1.0) -> np.ndarray:
-    """He-normal initial parameters in the packed layout W1[8][64], b1[64],
-    W2[64][64], b2[64], w3[64], b3 (inputs 6 and 7 are unused features)."""
-    g = np.random.default_rng(seed)
-    W1 = g.normal(0.0, scale * np.sqrt(2.0 / 6), (IN, H))
-    W1[6:, :] = 0.0
-    W2 = g.normal(0.0, scale * np.sqrt(2.0 / H), (H, H))
-    w3 = g.normal(0.0, scale * np.sqrt(1.0 / H), H)
-    p = np.concatenate([W1.ravel(), np.full(H, 0.05), W2.ravel(), np.full(H, 0.05), w3, np.zeros(1)])
+    """Initial parameters (float32, packed layout) from the seeded generator."""
+    p = network_params(seed, scale)
     assert p.size == MLP_NPARAM
     return p.astype(np.float32)
 

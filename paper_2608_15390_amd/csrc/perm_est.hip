@@ -1026,7 +1026,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         PE_HIP(hipGetLastError());
         if (kernel_events) PE_HIP(hipEventRecord(h->evk1, q));
         // per-matrix statistics over each matrix's slice of the outputs
-        if (res) k_reduce_stats<<<(unsigned)count, 1024, 0, q>>>(lb.seg, lb.stats);
+        if (res) k_reduce_stats<<<(unsigned)count, kWave, 0, q>>>(lb.seg, lb.stats);
         PE_HIP(hipGetLastError());
         return PE_OK;
     };

@@ -4,8 +4,8 @@
 //   L  = max ln X over survivors, S1 = sum e^{lnX - L}, S2 = sum e^{2(lnX-L)}
 //   ln mean = L + ln S1 - ln M; CV^2 = M (M S2 / S1^2 - 1) / (M - 1);
 //   RSE = CV / sqrt(M); ESS = S1^2 / S2; p_match = n_alive / M.
-// One block per segment (matrix), all segments in one launch; each thread
-// owns a strided subset and the block combines partials in a fixed tree
+// One wave per segment (matrix), all segments in one launch; each lane owns
+// a strided subset and the wave combines partials in a fixed butterfly
 // order, so results do not depend on scheduling.
 #pragma once
 #include "device.hpp"
@@ -36,29 +36,26 @@ struct KSum {
     __device__ double value() const { return s + c; }
 };
 
+// Butterfly combination of one value per lane across the wave: every lane
+// ends with op over all 64, combined in the same fixed order (xor distances
+// 32, 16, .., 1), so the result does not depend on scheduling.
 template <typename T, typename Op>
-__device__ T block_reduce(T v, T *buf, Op op) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (t < o) buf[t] = op(buf[t], buf[t + o]);
-        __syncthreads();
-    }
-    const T r = buf[0];
-    __syncthreads();
-    return r;
+__device__ T wave_allreduce(T v, Op op) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o));
+    return v;
 }
 
-__global__ void __launch_bounds__(1024) k_reduce_stats(const ReduceSeg *segs, DevStats *out) {
-    __shared__ double dbuf[1024];
-    __shared__ long long ibuf[1024];
+// One wave per segment (matrix): a single-wave block with no LDS, so the
+// reduction can start on any CU with a free wave slot even while persistent
+// trajectory kernels of other streams hold the chip's LDS.
+__global__ void __launch_bounds__(64) k_reduce_stats(const ReduceSeg *segs, DevStats *out) {
     const ReduceSeg sg = segs[blockIdx.x];
     const double *logw = sg.logw;
     const uint8_t *alive = sg.alive;
     const int32_t *counters = sg.counters;
     const int64_t lo = 0, hi = sg.count;
-    const int t = threadIdx.x, B = blockDim.x;
+    const int t = threadIdx.x, B = kWave;
     auto dmax = [](double a, double b) { return a > b ? a : b; };
     auto dadd = [](double a, double b) { return a + b; };
     auto iadd = [](long long a, long long b) { return a + b; };
@@ -72,12 +69,12 @@ __global__ void __launch_bounds__(1024) k_reduce_stats(const ReduceSeg *segs, De
             c2 += counters[4 * q + 2]; c3 += counters[4 * q + 3];
         }
     }
-    L = block_reduce(L, dbuf, dmax);
-    na = block_reduce(na, ibuf, iadd);
-    c0 = block_reduce(c0, ibuf, iadd);
-    c1 = block_reduce(c1, ibuf, iadd);
-    c2 = block_reduce(c2, ibuf, iadd);
-    c3 = block_reduce(c3, ibuf, iadd);
+    L = wave_allreduce(L, dmax);
+    na = wave_allreduce(na, iadd);
+    c0 = wave_allreduce(c0, iadd);
+    c1 = wave_allreduce(c1, iadd);
+    c2 = wave_allreduce(c2, iadd);
+    c3 = wave_allreduce(c3, iadd);
 
     KSum s1, s2, m1;
     for (int64_t q = lo + t; q < hi; q += B) {
@@ -87,9 +84,9 @@ __global__ void __launch_bounds__(1024) k_reduce_stats(const ReduceSeg *segs, De
         s2.add(a * a);
         m1.add(logw[q]);
     }
-    const double S1 = block_reduce(s1.value(), dbuf, dadd);
-    const double S2 = block_reduce(s2.value(), dbuf, dadd);
-    const double M1 = block_reduce(m1.value(), dbuf, dadd);
+    const double S1 = wave_allreduce(s1.value(), dadd);
+    const double S2 = wave_allreduce(s2.value(), dadd);
+    const double M1 = wave_allreduce(m1.value(), dadd);
     const double mean = na > 0 ? M1 / (double)na : 0.0;
     KSum vv;
     for (int64_t q = lo + t; q < hi; q += B) {
@@ -97,7 +94,7 @@ __global__ void __launch_bounds__(1024) k_reduce_stats(const ReduceSeg *segs, De
         const double d = logw[q] - mean;
         vv.add(d * d);
     }
-    const double V = block_reduce(vv.value(), dbuf, dadd);
+    const double V = wave_allreduce(vv.value(), dadd);
 
     if (t == 0) {
         DevStats r;

@@ -19,12 +19,18 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // so every LDS access or cross-lane exchange that waits for its result would
 // also wait for all outstanding HBM loads and stores. Device code therefore
 // re-types such pointers as global (address space 1) or LDS (3) ones.
+// Argument blocks, written by the host before a launch and never by the
+// kernels, are read through the constant address space (4): the compiler
+// then reads their fields with scalar loads that need not wait for the
+// trajectory's own stores, and may keep or re-read them at will.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PE_G __attribute__((address_space(1)))
 #define PE_L __attribute__((address_space(3)))
+#define PE_C __attribute__((address_space(4)))
 #else
 #define PE_G
 #define PE_L
+#define PE_C
 #endif
 constexpr int kAsGlobal = 1, kAsLds = 3;
 template <int AS, class T> struct AsPtr { using type = PE_G T *; };
@@ -34,6 +40,8 @@ template <int AS, class T>
 __device__ __forceinline__ as_ptr<AS, T> to_as(T *p) { return (as_ptr<AS, T>)p; }
 template <class T>
 __device__ __forceinline__ PE_G T *gptr(T *p) { return (PE_G T *)p; }
+template <class T>
+__device__ __forceinline__ const PE_C T *cptr(const T *p) { return (const PE_C T *)p; }
 // the same address space with another element type
 template <class U, class T>
 __device__ __forceinline__ PE_G U *recast(PE_G T *p) { return (PE_G U *)p; }

@@ -506,14 +506,24 @@ void launch_rows(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipSt
 }
 
 // four-trajectories-per-wave kernel of the learned proposal
-const void *rows_learned_kernel_fn(bool wt) {
-    return wt ? (const void *)&traj_rows_learned_kernel<true> : (const void *)&traj_rows_learned_kernel<false>;
+// l0g: the min-tree's lowest level in the state slot (TrajArgs::l0_state)
+const void *rows_learned_kernel_fn(bool wt, bool l0g) {
+    if (l0g)
+        return wt ? (const void *)&traj_rows_learned_kernel<true, kAsGlobal>
+                  : (const void *)&traj_rows_learned_kernel<false, kAsGlobal>;
+    return wt ? (const void *)&traj_rows_learned_kernel<true, kAsLds>
+              : (const void *)&traj_rows_learned_kernel<false, kAsLds>;
 }
 
-void launch_rows_learned(bool wt, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+void launch_rows_learned(bool wt, bool l0g, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
                          const BatchArgs *b) {
-    if (wt) traj_rows_learned_kernel<true><<<blocks, threads, shmem, s>>>(b);
-    else traj_rows_learned_kernel<false><<<blocks, threads, shmem, s>>>(b);
+    if (l0g) {
+        if (wt) traj_rows_learned_kernel<true, kAsGlobal><<<blocks, threads, shmem, s>>>(b);
+        else traj_rows_learned_kernel<false, kAsGlobal><<<blocks, threads, shmem, s>>>(b);
+    } else {
+        if (wt) traj_rows_learned_kernel<true, kAsLds><<<blocks, threads, shmem, s>>>(b);
+        else traj_rows_learned_kernel<false, kAsLds><<<blocks, threads, shmem, s>>>(b);
+    }
 }
 
 // upper bound on resident trajectory waves per CU for the default launch shape
@@ -911,7 +921,8 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     }
     const bool rows = rows_learned || (rows_ok && sched->sk_policy == PE_SK_NONE &&
                                        block_fixed + 4 * (4 * tree_bytes + (size_t)lds_cap) <= lds4);
-    const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt) : rows_kernel_fn(wt);
+    const bool l0g = rows_learned && l0_rows;  // learned rows with level 0 in the state slot
+    const void *rows_fn = rows_learned ? rows_learned_kernel_fn(wt, l0g) : rows_kernel_fn(wt);
     const int tpw = rows ? 4 : 1;  // trajectories per wave
     // One trajectory per wave: a large matrix keeps the lowest internal level
     // of its min-tree (one node per 256 leaves, the bulk of the tree) in its
@@ -1020,7 +1031,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(lb.work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
         if (kernel_events) PE_HIP(hipEventRecord(h->evk0, q));
-        if (rows_learned) launch_rows_learned(wt, blocks, wpb * kWave, shmem, q, lb.batch);
+        if (rows_learned) launch_rows_learned(wt, l0g, blocks, wpb * kWave, shmem, q, lb.batch);
         else if (rows) launch_rows(wt, blocks, wpb * kWave, shmem, q, lb.batch);
         else launch_traj(sk_kind, dm, wt, blocks, wpb * kWave, shmem, q, lb.batch);
         PE_HIP(hipGetLastError());

@@ -105,49 +105,95 @@ __device__ __forceinline__ int row_owner(int32_t f, int32_t off) {
     return lo;
 }
 
+// the scaling value of an unscaled matrix, at a fixed global address
+__device__ const float kUnitScale = 1.0f;
+
 // One row's trajectory state and views (all values uniform within the row).
+// L0AS: address space of the min-tree's lowest internal level (LDS, or the
+// row's state slot in global memory); the levels above it are in LDS.  Each
+// level is reached through a pointer of its own address space, so no tree
+// access becomes a flat instruction (a flat access also holds up every later
+// wait for LDS results until its memory round trip ends).
+template <int L0AS>
 struct RowTraj {
-    const PE_G TrajArgs &a;
+    const PE_C TrajArgs &a;
     GMat M;
     PE_G uint16_t *deg;
     PE_G int32_t *lst_a, *lst_b;
-    uint32_t *tree;
+    PE_L uint32_t *tree;          // the internal levels kept in LDS
     int32_t n;
-    uint32_t *lvl0;  // the tree's lowest internal level: in LDS, or in the state slot
+    as_ptr<L0AS, uint32_t> lvl0;  // the lowest internal level
 
-    __device__ uint32_t *level(int k) const { return k == 0 ? lvl0 : tree + a.tree.off[k]; }
+    // node i of internal level k: read, write, atomic minimum
+    __device__ uint32_t node(int k, int32_t i) const { return k == 0 ? lvl0[i] : tree[a.tree.off[k] + i]; }
+    __device__ void set_node(int k, int32_t i, uint32_t v) const {
+        if (k == 0) lvl0[i] = v;
+        else tree[a.tree.off[k] + i] = v;
+    }
+    __device__ void min_node(int k, int32_t i, uint32_t v) const {
+        if (k == 0) atomicMin(lvl0 + i, v);
+        else atomicMin(tree + a.tree.off[k] + i, v);
+    }
+    // nodes base .. base + 3 of level k (base a multiple of 4), read by every
+    // lane with one choice of address space for all four, so the reads issue
+    // together; values past the level's end are unspecified (callers mask
+    // them).  Level 0 in the state slot is padded to whole 64-node blocks and
+    // 256-byte aligned: one 16-byte load.
+    __device__ void nodes4(int k, int32_t base, uint32_t (&w)[4]) const {
+        if (L0AS == kAsGlobal && k == 0) {
+            const uint4 q = *(const PE_G uint4 *)(lvl0 + base);
+            w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+        } else {
+            const int32_t last = a.tree.size[k] - 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i] = node(k, base + i < last ? base + i : last);
+        }
+    }
+    // The accessors below pick their array by a select rather than a branch:
+    // lanes of one row may read rows and columns alike, and a load in each
+    // arm of a divergent branch would be waited for at the join before the
+    // next load could issue.
     __device__ void list(int32_t x, int32_t &b, int32_t &e) const {
-        if (x < n) { b = M.row_ptr[x]; e = M.row_ptr[x + 1]; }
-        else { b = M.col_ptr[x - n]; e = M.col_ptr[x - n + 1]; }
+        const bool row = x < n;
+        const PE_G int32_t *ptr = row ? M.row_ptr : M.col_ptr;
+        const int32_t i = row ? x : x - n;
+        b = ptr[i];
+        e = ptr[i + 1];
     }
     template <bool WT>
     __device__ void entry(bool row, int32_t p, int32_t &y, float &bv) const {
-        if (row) { y = n + M.col_idx[p]; bv = WT ? M.val[p] : 1.0f; }
-        else { y = M.row_idx[p]; bv = WT ? M.val_csc[p] : 1.0f; }
+        y = (row ? M.col_idx : M.row_idx)[p] + (row ? n : 0);
+        bv = WT ? (row ? M.val : M.val_csc)[p] : 1.0f;
     }
     __device__ float scale0(int32_t y) const {
         if (y < n) return a.r0 ? gptr(a.r0)[y] : 1.0f;
         return a.c0 ? gptr(a.c0)[y - n] : 1.0f;
     }
+    // the outer scaling of a vertex known to be a row / a column, read
+    // without a branch (an unscaled matrix reads a constant 1)
+    __device__ float scale_row(int32_t x) const { return *(a.r0 ? gptr(a.r0) + x : gptr(&kUnitScale)); }
+    __device__ float scale_col(int32_t x) const { return *(a.c0 ? gptr(a.c0) + (x - n) : gptr(&kUnitScale)); }
     __device__ void tree_lower(int32_t x, uint32_t d) const {
-        atomicMin(level(0) + (x >> 8), d);
-        if (a.tree.levels > 1) atomicMin(level(1) + (x >> 14), d);
-        if (a.tree.levels > 2) atomicMin(level(2) + (x >> 20), d);
+        min_node(0, x >> 8, d);
+        if (a.tree.levels > 1) min_node(1, x >> 14, d);
+        if (a.tree.levels > 2) min_node(2, x >> 20, d);
     }
     // min over nodes [64 h, 64 h + 64) of level k (4 per lane)
     __device__ uint32_t block_min(int k, int32_t h) const {
         const int32_t base = 64 * h + 4 * row_lane();
+        uint32_t w[4];
+        nodes4(k, base, w);
         uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (base + i < a.tree.size[k]) { const uint32_t w = level(k)[base + i]; m = w < m ? w : m; }
+            if (base + i < a.tree.size[k]) m = w[i] < m ? w[i] : m;
         return row_min_u32(m);
     }
     __device__ void refresh_upper(int32_t g) const {
         for (int k = 1; k < a.tree.levels; ++k) {
             const int32_t h = g >> 6;
             const uint32_t m = block_min(k - 1, h);
-            if (row_lane() == 0) level(k)[h] = m;
+            if (row_lane() == 0) set_node(k, h, m);
             wave_fence();
             g = h;
         }
@@ -220,8 +266,8 @@ __device__ __forceinline__ uint64_t scaled_weight(float s, float smax, bool unif
 template <bool WT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 traj_rows_kernel(const BatchArgs *__restrict__ bp) {
-    const PE_G BatchArgs &B = *gptr(bp);
-    const PE_G TrajArgs &a = gptr(B.mats)[0];
+    const PE_C BatchArgs &B = *cptr(bp);
+    const PE_C TrajArgs &a = cptr(B.mats)[0];
     extern __shared__ __align__(16) char smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int r = row_id(), rl = row_lane();
@@ -229,9 +275,9 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
     char *mine = smem + (size_t)wave * 4 * (size_t)B.lds_tree_bytes;
     PE_G char *state = gptr(B.hbm_state) + (((uint64_t)blockIdx.x * B.waves_per_block + wave) * 4 + r) * B.hbm_stride;
     const auto &L = a.st;
-    uint32_t *tree_row = reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
-    const RowTraj T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
-                    recast<int32_t>(state + L.lst_b), tree_row, n, tree_row + a.tree.off[0]};
+    PE_L uint32_t *tree_row = (PE_L uint32_t *)reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
+    const RowTraj<kAsLds> T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
+                            recast<int32_t>(state + L.lst_b), tree_row, n, tree_row + a.tree.off[0]};
     Work work;
     // per-row trajectory registers (uniform within the row)
     int phase = 0;  // 0 claim, 1 running, 2 no more work
@@ -285,9 +331,11 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                     // first node of the block [64 g, 64 g + 64) of level kk holding m
                     const int32_t base = 64 * g + 4 * rl;
                     int j = 4;
+                    uint32_t w[4];
+                    T.nodes4(kk, base, w);
 #pragma unroll
                     for (int i = 3; i >= 0; --i)
-                        if (base + i < a.tree.size[kk] && T.level(kk)[base + i] == m) j = i;
+                        if (w[i] == m && base + i < a.tree.size[kk]) j = i;
                     const uint32_t bits = row_bits(ballot(j < 4));
                     const int src = __ffs(bits) - 1;
                     const int js = row_read(j, src < 0 ? 0 : src);
@@ -470,7 +518,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                     }
                 }
                 const int32_t gu = u >> 8;
-                const uint32_t l1u_before = T.level(0)[gu];
+                const uint32_t l1u_before = T.lvl0[gu];
                 // u's group needs a new minimum when u is it: read its leaves
                 // before this step's stores (stale values are only higher;
                 // the new degrees and u are patched in below)
@@ -531,7 +579,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 {
                     uint32_t mm = min16_skip(lq0, lq1, 256 * gsel + 16 * rl, v, u);
                     mm = row_min_u32(mm < dec_min_g ? mm : dec_min_g);
-                    if (rl == 0) T.level(0)[gsel] = mm;
+                    if (rl == 0) T.lvl0[gsel] = mm;
                     wave_fence();
                     // the upper levels hold every lowered value already
                     if (mm > m_sel) T.refresh_upper(gsel);
@@ -539,7 +587,7 @@ traj_rows_kernel(const BatchArgs *__restrict__ bp) {
                 if (refresh_u) {
                     uint32_t mu = min16_skip(uq0, uq1, 256 * gu + 16 * rl, v, u);
                     mu = row_min_u32(mu < dec_min_u ? mu : dec_min_u);
-                    if (rl == 0) T.level(0)[gu] = mu;
+                    if (rl == 0) T.lvl0[gu] = mu;
                     wave_fence();
                     if (mu > d_u) T.refresh_upper(gu);
                 }

@@ -52,8 +52,8 @@ struct RowNbrCache {
 // floor(2^20 / deg w) and c2_u = #{w != v : deg w <= 2}: the row's
 // candidates' lists flattened over its 16 lanes and summed per owner with a
 // segmented scan (integer sums: the result does not depend on the order).
-template <bool WT>
-__device__ __forceinline__ void row_candidate_stats(const RowTraj &T, bool ok, int32_t y, int32_t yb, int32_t ye,
+template <bool WT, int L0AS>
+__device__ __forceinline__ void row_candidate_stats(const RowTraj<L0AS> &T, bool ok, int32_t y, int32_t yb, int32_t ye,
                                                     int32_t v, uint64_t &s_u, int32_t &c2_u, RowNbrCache &nc) {
     const int rl = row_lane();
     const int32_t len = ok ? ye - yb : 0;
@@ -79,14 +79,18 @@ __device__ __forceinline__ void row_candidate_stats(const RowTraj &T, bool ok, i
             const int32_t o_off = row_read(off, own[i]);
             const int32_t o_yb = row_read(yb, own[i]);
             const bool o_row = row_read(y_row, own[i]) != 0;
-            w[i] = -1;
-            if (valid[i]) {
-                float bv;
-                T.entry<false>(o_row, o_yb + (f - o_off), w[i], bv);
-            }
+            // every lane loads (an invalid one reads entry 0), then masks:
+            // no branch, so both passes' reads issue before either is waited for
+            float bv;
+            T.template entry<false>(o_row, valid[i] ? o_yb + (f - o_off) : 0, w[i], bv);
+            if (!valid[i]) w[i] = -1;
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i) dw[i] = valid[i] ? (uint32_t)T.deg[w[i]] : (uint32_t)kRetired;
+        for (int i = 0; i < 2; ++i) {
+            // every lane loads (an invalid one reads vertex 0), then masks
+            const uint32_t d = (uint32_t)T.deg[valid[i] ? w[i] : 0];
+            dw[i] = valid[i] ? d : (uint32_t)kRetired;
+        }
         if (base == 0) {
             nc.w0 = w[0]; nc.d0 = dw[0];
             nc.w1 = w[1]; nc.d1 = dw[1];
@@ -124,14 +128,15 @@ __device__ __forceinline__ void row_candidate_stats(const RowTraj &T, bool ok, i
 // level-1 node holds the minimum of its 256 leaves together with the
 // position of the first leaf of that degree, so selection names the vertex
 // from LDS alone; higher levels hold degrees.
+template <int L0AS>
 struct ArgTree {
-    const RowTraj &T;
+    const RowTraj<L0AS> &T;
     __device__ uint32_t deg_at(int k, uint32_t val) const { return k == 0 ? val >> 8 : val; }
     // a decrement of vertex y to degree nd
     __device__ void lower(int32_t y, uint32_t nd) const {
-        atomicMin(T.level(0) + (y >> 8), (nd << 8) | (uint32_t)(y & 255));
-        if (T.a.tree.levels > 1) atomicMin(T.level(1) + (y >> 14), nd);
-        if (T.a.tree.levels > 2) atomicMin(T.level(2) + (y >> 20), nd);
+        T.min_node(0, y >> 8, (nd << 8) | (uint32_t)(y & 255));
+        if (T.a.tree.levels > 1) T.min_node(1, y >> 14, nd);
+        if (T.a.tree.levels > 2) T.min_node(2, y >> 20, nd);
     }
     // recompute the degree chain above level-1 node g
     __device__ void refresh_upper(int32_t g) const {
@@ -139,15 +144,16 @@ struct ArgTree {
         for (int k = 1; k < T.a.tree.levels; ++k) {
             const int32_t h = g >> 6;
             const int32_t base = 64 * h + 4 * rl;
+            uint32_t raw[4];
+            T.nodes4(k - 1, base, raw);
             uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (base + i < T.a.tree.size[k - 1]) {
-                    const uint32_t w = deg_at(k - 1, T.level(k - 1)[base + i]);
-                    m = w < m ? w : m;
-                }
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t w = deg_at(k - 1, raw[i]);
+                if (base + i < T.a.tree.size[k - 1]) m = w < m ? w : m;
+            }
             m = row_min_u32(m);
-            if (rl == 0) T.level(k)[h] = m;
+            if (rl == 0) T.set_node(k, h, m);
             wave_fence();
             g = h;
         }
@@ -174,12 +180,14 @@ __device__ __forceinline__ uint32_t argmin16_skip(const uint4 &q0, const uint4 &
     return m;
 }
 
-// The learned proposal, four trajectories per wave; WT: weighted entries.
-template <bool WT>
+// The learned proposal, four trajectories per wave; WT: weighted entries;
+// L0AS: where the min-tree's lowest level lives (kAsGlobal: the row's state
+// slot, as the launch chose for this matrix; kAsLds: with the levels above).
+template <bool WT, int L0AS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
-    const PE_G BatchArgs &B = *gptr(bp);
-    const PE_G TrajArgs &a = gptr(B.mats)[0];
+    const PE_C BatchArgs &B = *cptr(bp);
+    const PE_C TrajArgs &a = cptr(B.mats)[0];
     extern __shared__ __align__(16) char smem[];
     LearnedLds *lrn = reinterpret_cast<LearnedLds *>(smem);
     stage_weights<true>(&lrn->net, gptr(B.mlp));
@@ -197,12 +205,14 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
     const auto &L = a.st;
     // the tree's lowest level lives in the row's state slot when the launch
     // moved it there (LDS then holds the levels above, offsets from 0)
-    uint32_t *tree_row = reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
-    uint32_t *lvl0 = a.l0_state ? reinterpret_cast<uint32_t *>((char *)state + L.lvl0) : tree_row + a.tree.off[0];
-    const RowTraj T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
-                    recast<int32_t>(state + L.lst_b), tree_row, n, lvl0};
+    PE_L uint32_t *tree_row = (PE_L uint32_t *)reinterpret_cast<uint32_t *>(mine + (size_t)r * B.lds_tree_bytes);
+    as_ptr<L0AS, uint32_t> lvl0;
+    if constexpr (L0AS == kAsGlobal) lvl0 = recast<uint32_t>(state + L.lvl0);
+    else lvl0 = tree_row + a.tree.off[0];
+    const RowTraj<L0AS> T{a, GMat(a.A), recast<uint16_t>(state + L.deg), recast<int32_t>(state + L.lst_a),
+                          recast<int32_t>(state + L.lst_b), tree_row, n, lvl0};
     const double alpha = a.mix_alpha;
-    const ArgTree AT{T};
+    const ArgTree<L0AS> AT{T};
     Work work;
     // per-row trajectory registers (uniform within the row)
     int phase = 0;  // 0 claim, 1 running, 2 no more work
@@ -236,7 +246,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 const auto src = gptr(reinterpret_cast<const uint4 *>(a.deg0));
                 const auto dst = recast<uint4>(T.deg);
                 for (int32_t i = rl; i < a.n_leaf / 8; i += kRowLanes) dst[i] = src[i];
-                if (a.l0_state) {
+                if constexpr (L0AS == kAsGlobal) {
                     for (int32_t i = rl; i < a.tree.size[0]; i += kRowLanes) T.lvl0[i] = gptr(a.tree0a)[i];
                     for (int32_t i = rl; i < a.tree.total; i += kRowLanes)
                         T.tree[i] = gptr(a.tree0a)[a.tree_l1_src + i];
@@ -263,10 +273,10 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 // level 1 the code also carries the position of the vertex
                 const int top = a.tree.levels - 1;
                 const int32_t tb = 4 * rl;
-                uint32_t w4[4];
+                uint32_t raw4[4], w4[4];
+                T.nodes4(top, tb, raw4);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    w4[i] = tb + i < a.tree.size[top] ? AT.deg_at(top, T.level(top)[tb + i]) : 0xFFFFFFFFu;
+                for (int i = 0; i < 4; ++i) w4[i] = tb + i < a.tree.size[top] ? AT.deg_at(top, raw4[i]) : 0xFFFFFFFFu;
                 const uint32_t m = row_min_u32(min(min(w4[0], w4[1]), min(w4[2], w4[3])));
                 m_sel = m;
                 int32_t g = 0;
@@ -275,7 +285,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     uint32_t code = 0xFFFFFFFFu;
 #pragma unroll
                     for (int i = 3; i >= 0; --i)
-                        if (w4[i] == m) code = ((uint32_t)(tb + i) << 8) | (T.level(0)[tb + i] & 255u);
+                        if (w4[i] == m) code = ((uint32_t)(tb + i) << 8) | (raw4[i] & 255u);
                     const uint32_t cm = row_min_u32(code);
                     g = (int32_t)(cm >> 8);
                     pos = cm & 255u;
@@ -288,14 +298,12 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     for (int kk = top - 1; kk >= 0 && g >= 0; --kk) {
                         const int32_t base = 64 * g + tb;
                         code = 0xFFFFFFFFu;
+                        uint32_t val[4];
+                        T.nodes4(kk, base, val);
 #pragma unroll
-                        for (int i = 3; i >= 0; --i) {
-                            if (base + i < a.tree.size[kk]) {
-                                const uint32_t val = T.level(kk)[base + i];
-                                if (AT.deg_at(kk, val) == m)
-                                    code = kk == 0 ? (((uint32_t)(tb + i) << 8) | (val & 255u)) : (uint32_t)(tb + i);
-                            }
-                        }
+                        for (int i = 3; i >= 0; --i)
+                            if (base + i < a.tree.size[kk] && AT.deg_at(kk, val[i]) == m)
+                                code = kk == 0 ? (((uint32_t)(tb + i) << 8) | (val[i] & 255u)) : (uint32_t)(tb + i);
                         const uint32_t cm = row_min_u32(code);
                         if (cm == 0xFFFFFFFFu) {
                             g = -1;
@@ -331,7 +339,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
             if (!dead && fast_v) {
                 const int32_t p = vb + rl;
                 if (p < ve) {
-                    T.entry<WT>(v_row, p, cy, cbv);
+                    T.template entry<WT>(v_row, p, cy, cbv);
                     cd = T.deg[cy];
                     T.list(cy, cub, cue);  // issued with the degree load
                     cand = cd != kRetired;
@@ -344,7 +352,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     int32_t y = 0;
                     float bvv = 0.0f;
                     if (p < ve) {
-                        T.entry<WT>(v_row, p, y, bvv);
+                        T.template entry<WT>(v_row, p, y, bvv);
                         c0 = T.deg[y] != kRetired;
                     }
                     const uint32_t msk = row_bits(ballot(c0));
@@ -389,6 +397,10 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 uint64_t su;
                 int32_t c2;
                 RowNbrCache ncc;
+                // the candidate edge's outer scaling, read before the
+                // statistics so that its latency overlaps theirs
+                const int32_t rho = v_row ? v : y, gam = v_row ? y : v;
+                const float s_rho = T.scale_row(ok ? rho : 0), s_gam = T.scale_col(ok ? gam : n);
                 row_candidate_stats<WT>(T, ok, y, yb, ye, v, su, c2, ncc);
                 if (c == 0) nc = ncc;
                 // features into the wave's record area
@@ -397,10 +409,9 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 const int32_t rbase = rows_excl_prefix(__popc(okm), all_recs);
                 const int32_t rec = rbase + __popc(okm & ((1u << rl) - 1u));
                 if (ok) {
-                    const int32_t rho = v_row ? v : y, gam = v_row ? y : v;
                     float x[8];
-                    learned_features(x, v_row ? (uint32_t)kc : dy, v_row ? dy : (uint32_t)kc, T.scale0(rho),
-                                     T.scale0(gam), k4, v_row, su, c2);
+                    learned_features(x, v_row ? (uint32_t)kc : dy, v_row ? dy : (uint32_t)kc, s_rho, s_gam, k4, v_row,
+                                     su, c2);
                     uint4 pk;
                     pk.x = (uint32_t)(uint16_t)to_bf16(x[0]) | ((uint32_t)(uint16_t)to_bf16(x[1]) << 16);
                     pk.y = (uint32_t)(uint16_t)to_bf16(x[2]) | ((uint32_t)(uint16_t)to_bf16(x[3]) << 16);
@@ -531,7 +542,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                         const int32_t p = base + rl;
                         int32_t y = -1;
                         float bvv = 0.0f;
-                        if (p < ve) T.entry<WT>(v_row, p, y, bvv);
+                        if (p < ve) T.template entry<WT>(v_row, p, y, bvv);
                         const uint32_t hit = row_bits(ballot(p < ve && y == u));
                         if (hit) b_vu = row_read(bvv, __ffs(hit) - 1);
                     }
@@ -556,7 +567,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 // u's group needs a new minimum when u is its recorded argmin:
                 // read its leaves before this step's stores (stale values are
                 // only higher; the new degrees and u are patched in below)
-                const bool refresh_u = gu != gsel && T.level(0)[gu] == ((d_u << 8) | (uint32_t)(u & 255));
+                const bool refresh_u = gu != gsel && T.lvl0[gu] == ((d_u << 8) | (uint32_t)(u & 255));
                 uint4 uq0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), uq1 = uq0;
                 if (refresh_u) T.load_leaves(gu, uq0, uq1);
                 // N_t(u) \ {v}: from the statistics' cache when u's list lies
@@ -592,7 +603,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                     const int32_t p = ub + rl;
                     if (p < ue) {
                         float bvv;
-                        T.entry<false>(u_row, p, by, bvv);
+                        T.template entry<false>(u_row, p, by, bvv);
                         bd = T.deg[by];
                         take = by != v && bd != kRetired;
                     }
@@ -604,7 +615,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                         int32_t y = 0;
                         if (p < ue) {
                             float bvv;
-                            T.entry<false>(u_row, p, y, bvv);
+                            T.template entry<false>(u_row, p, y, bvv);
                             tk = y != v && T.deg[y] != kRetired;
                         }
                         const uint32_t msk = row_bits(ballot(tk));
@@ -670,7 +681,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 {
                     uint32_t mm = argmin16_skip(lq0, lq1, gsel, v, u);
                     mm = row_min_u32(mm < dec_min_g ? mm : dec_min_g);
-                    if (rl == 0) T.level(0)[gsel] = mm;
+                    if (rl == 0) T.lvl0[gsel] = mm;
                     wave_fence();
                     // the upper levels hold every lowered value already
                     if ((mm >> 8) > m_sel) AT.refresh_upper(gsel);
@@ -678,7 +689,7 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
                 if (refresh_u) {
                     uint32_t mu = argmin16_skip(uq0, uq1, gu, v, u);
                     mu = row_min_u32(mu < dec_min_u ? mu : dec_min_u);
-                    if (rl == 0) T.level(0)[gu] = mu;
+                    if (rl == 0) T.lvl0[gu] = mu;
                     wave_fence();
                     if ((mu >> 8) > d_u) AT.refresh_upper(gu);
                 }

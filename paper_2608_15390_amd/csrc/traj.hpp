@@ -40,7 +40,8 @@ struct DevMat {
 struct GMat {
     const PE_G int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *csc2csr, *edge_row;
     const PE_G float *val, *val_csc;
-    __device__ explicit GMat(const PE_G DevMat &A)
+    template <class DM>
+    __device__ explicit GMat(const DM &A)
         : row_ptr(gptr(A.row_ptr)), col_idx(gptr(A.col_idx)), col_ptr(gptr(A.col_ptr)), row_idx(gptr(A.row_idx)),
           csc2csr(gptr(A.csc2csr)), edge_row(gptr(A.edge_row)), val(gptr(A.val)), val_csc(gptr(A.val_csc)) {}
 };

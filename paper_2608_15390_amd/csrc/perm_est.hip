@@ -621,7 +621,7 @@ int new_handle(const perm_est_options *opts, perm_est **out) {
     char *scr = nullptr;
     if (int rc0 = noalloc_scratch(h->device, &scr)) return rc0;
     int rc;
-    if ((rc = dalloc(&h->work, 2)) || (rc = dalloc(&h->work_totals, kWorkTotals)) || (rc = dalloc(&h->flags, 8)) ||
+    if ((rc = dalloc(&h->work, 3)) || (rc = dalloc(&h->work_totals, kWorkTotals)) || (rc = dalloc(&h->flags, 8)) ||
         (rc = dalloc(&h->batch_dev, 1)) || (rc = dalloc(&h->rec_ctr, 2)))
         return rc;
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
@@ -1023,11 +1023,18 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
     PE_HIP(hipMemcpyAsync(lb.item_off, h->item_off_host.data(), sizeof(int64_t) * (count + 1),
                           hipMemcpyHostToDevice, s));
     PE_HIP(hipMemcpyAsync(lb.seg, h->seg_host.data(), sizeof(ReduceSeg) * count, hipMemcpyHostToDevice, s));
+    // the learned row kernel reduces its statistics in its last block: at
+    // its register use no other wave fits beside three of its own on a SIMD,
+    // so a separate reduction would wait for one of them to end
+    const bool fused_stats = rows_learned && res != nullptr;
+    B.seg = fused_stats ? lb.seg : nullptr;
+    B.stats = fused_stats ? lb.stats : nullptr;
+    B.blocks_done = lb.work + 2;
     PE_HIP(hipMemcpyAsync(lb.batch, &B, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
-    // the launch sequence; counters are cleared by kernels (no memset nodes)
+    // the launch sequence; counters are cleared by kernels (no memset nodes):
+    // work[0] item counter, [1] error bits, [2] finished blocks
     auto enqueue = [&](hipStream_t q, bool kernel_events) -> int {
-        k_set_u32<<<1, 1, 0, q>>>(lb.work, 0u);
-        k_set_u32<<<1, 1, 0, q>>>(lb.work + 1, 0u);
+        k_fill_i32<<<1, 64, 0, q>>>(3, reinterpret_cast<int32_t *>(lb.work), 0);
         k_fill_i32<<<1, 64, 0, q>>>(2 * kWorkTotals, reinterpret_cast<int32_t *>(lb.work_totals), 0);
         if (rec) k_fill_i32<<<1, 64, 0, q>>>(4, reinterpret_cast<int32_t *>(h->rec_ctr), 0);
         if (kernel_events) PE_HIP(hipEventRecord(h->evk0, q));
@@ -1037,7 +1044,7 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         PE_HIP(hipGetLastError());
         if (kernel_events) PE_HIP(hipEventRecord(h->evk1, q));
         // per-matrix statistics over each matrix's slice of the outputs
-        if (res) k_reduce_stats<<<(unsigned)count, kWave, 0, q>>>(lb.seg, lb.stats);
+        if (res && !fused_stats) k_reduce_stats<<<(unsigned)count, kWave, 0, q>>>(lb.seg, lb.stats);
         PE_HIP(hipGetLastError());
         return PE_OK;
     };
@@ -1485,7 +1492,7 @@ int perm_est_run_range_noalloc(perm_est_t *h, int64_t first, int64_t count, uint
         return p;
     };
     LaunchBufs lb;
-    lb.work = reinterpret_cast<uint32_t *>(take(2 * sizeof(uint32_t)));
+    lb.work = reinterpret_cast<uint32_t *>(take(3 * sizeof(uint32_t)));
     lb.work_totals = reinterpret_cast<unsigned long long *>(take(kWorkTotals * sizeof(unsigned long long)));
     lb.args = reinterpret_cast<TrajArgs *>(take(sizeof(TrajArgs)));
     lb.batch = reinterpret_cast<BatchArgs *>(take(sizeof(BatchArgs)));

@@ -46,16 +46,13 @@ __device__ T wave_allreduce(T v, Op op) {
     return v;
 }
 
-// One wave per segment (matrix): a single-wave block with no LDS, so the
-// reduction can start on any CU with a free wave slot even while persistent
-// trajectory kernels of other streams hold the chip's LDS.
-__global__ void __launch_bounds__(64) k_reduce_stats(const ReduceSeg *segs, DevStats *out) {
-    const ReduceSeg sg = segs[blockIdx.x];
+// One wave reduces one segment (matrix) into *out.
+__device__ void reduce_segment(const ReduceSeg &sg, DevStats *out) {
     const double *logw = sg.logw;
     const uint8_t *alive = sg.alive;
     const int32_t *counters = sg.counters;
     const int64_t lo = 0, hi = sg.count;
-    const int t = threadIdx.x, B = kWave;
+    const int t = lane_id(), B = kWave;
     auto dmax = [](double a, double b) { return a > b ? a : b; };
     auto dadd = [](double a, double b) { return a + b; };
     auto iadd = [](long long a, long long b) { return a + b; };
@@ -117,7 +114,32 @@ __global__ void __launch_bounds__(64) k_reduce_stats(const ReduceSeg *segs, DevS
             r.ess = S1 * S1 / S2;
             r.var_logw = na > 1 ? V / (double)(na - 1) : 0.0;
         }
-        out[blockIdx.x] = r;
+        *out = r;
+    }
+}
+
+// One wave per segment: a single-wave block with no LDS, so the reduction
+// can start on any CU with a free wave slot even while persistent trajectory
+// kernels of other streams hold the chip's LDS.
+__global__ void __launch_bounds__(64) k_reduce_stats(const ReduceSeg *segs, DevStats *out) {
+    reduce_segment(segs[blockIdx.x], out + blockIdx.x);
+}
+
+// The launch's statistics from inside a persistent trajectory kernel of one
+// matrix: the last block to finish reduces every block's outputs with its
+// first wave.  A register-heavy trajectory kernel (its own launch or those
+// of other streams) can leave no SIMD room for a separate reduction wave,
+// which then waits for one of its waves to end; here the reduction runs on
+// waves already resident.  Every thread of the block must reach this call;
+// `flag` is a word of the block's LDS that no wave reads any more.
+__device__ void reduce_in_last_block(const ReduceSeg *seg, DevStats *stats, uint32_t *blocks_done, uint32_t *flag) {
+    __threadfence();  // this thread's outputs, device-wide, before the count
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = atomicAdd(blocks_done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (*flag && threadIdx.x < kWave) {
+        __threadfence();  // every block's outputs before reading them
+        reduce_segment(*seg, stats);
     }
 }
 

@@ -722,6 +722,9 @@ traj_rows_learned_kernel(const BatchArgs *__restrict__ bp) {
         atomicAdd(B.work_totals + 5, (unsigned long long)work.mlp_tiles);
         atomicAdd(B.work_totals + 6, (unsigned long long)work.scan_v);
     }
+    // the launch's statistics, reduced by the last block to finish (its flag
+    // in the softmax table's first word, unused once every wave is done)
+    if (B.stats) reduce_in_last_block(B.seg, B.stats, B.blocks_done, lrn->etab);
 }
 
 }  // namespace pe

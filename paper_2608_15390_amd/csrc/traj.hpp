@@ -24,6 +24,7 @@
 // minimum degree with the smallest id.
 #pragma once
 #include "device.hpp"
+#include "reduce.hpp"
 #include "mlp.hpp"
 
 namespace pe {
@@ -1807,6 +1808,11 @@ struct BatchArgs {
     int32_t waves_per_block;
     const float *mlp;         // learned proposal parameters (staged per block), or nullptr
     const int64_t *etab;      // learned proposal's softmax table (staged per block)
+    // statistics reduced by the kernel's last block (the learned row
+    // kernel), or nullptr: a separate reduction kernel follows
+    const ReduceSeg *seg;
+    DevStats *stats;
+    uint32_t *blocks_done;    // finished-block counter (zeroed before launch)
 };
 
 constexpr int kMlpWaveBytes = (int)sizeof(WaveScratch);

@@ -49,12 +49,14 @@ HBM_PEAK_GBS = 8000.0
 
 KERNEL_SOURCES = ["paper_2608_15390_amd/csrc/traj.hpp", "paper_2608_15390_amd/csrc/device.hpp",
                   "paper_2608_15390_amd/csrc/mlp.hpp", "paper_2608_15390_amd/csrc/rows.hpp",
-                  "paper_2608_15390_amd/csrc/rows_learned.hpp"]
+                  "paper_2608_15390_amd/csrc/rows_learned.hpp", "paper_2608_15390_amd/csrc/reduce.hpp"]
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-# the dominant kernel of each timed method on the large workload (one
-# matrix of n = 1e5: four trajectories per wave for the network-only
-# learned proposal, one per wave for the local repair)
-KERNEL_NAME = {"learned": "pe::traj_rows_learned_kernel<false>", "plain": "pe::traj_kernel<3, false, false>"}
+# the dominant kernel of each timed schedule on the large workload (one
+# matrix of n = 1e5: four trajectories per wave for the network-only learned
+# proposal, its min-tree's lowest level in the state slot, and for the
+# unscaled plain estimator; one per wave for the local repair)
+KERNEL_NAME = {"learned": "pe::traj_rows_learned_kernel<false, 1>", "local_nodm": "pe::traj_kernel<3, false, false>",
+               "plain": "pe::traj_rows_kernel<false>"}
 # algorithmic FLOPs of one 16-candidate tile through the network (8 -> 64 -> 64 -> 1)
 FLOP_PER_TILE = 2 * 16 * (8 * 64 + 64 * 64 + 64)
 
@@ -931,7 +933,7 @@ def main() -> int:
         "training": dict(tinfo, matrices="512 x (n=1000, avg degree 6)", teacher="local_nodm (local SK repair per step)",
                          mix_alpha=LR.MIX_ALPHA),
         "roofline": {
-            "kernel": KERNEL_NAME.get(args.method, "pe::traj_kernel"),
+            "kernel": KERNEL_NAME.get(sched_name, "pe::traj_kernel"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

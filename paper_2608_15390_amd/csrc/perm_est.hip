@@ -897,15 +897,23 @@ int launch(perm_est *h, const perm_est_schedule *sched, uint64_t seed, std::vect
         a.tree = up;
         return PE_OK;
     };
-    // learned rows: four trees per wave would cap the CU at fewer waves than
-    // its registers allow (84 VGPRs: 24 waves), so the lowest tree level goes
-    // to the row's state slot (one more dependent load per selection, three
-    // times the waves in flight)
+    // learned rows: when four whole trees per wave would let fewer blocks
+    // share a CU's LDS than the kernel's registers allow, the lowest tree
+    // level goes to the row's state slot (one more dependent load per
+    // selection, more waves in flight)
     const bool learned_rows_cand = rows_ok && learned && !gated;
     bool l0_rows = false;
     size_t row_tree_bytes = tree_bytes;
+    int reg_blocks = 0;  // resident 4-wave blocks per CU as registers allow
+    if (learned_rows_cand &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&reg_blocks, rows_learned_kernel_fn(wt, false), 4 * kWave,
+                                                      0) != hipSuccess ||
+         reg_blocks < 1)) {
+        (void)hipGetLastError();
+        reg_blocks = 3;
+    }
     if (learned_rows_cand && prep[0]->tree.levels >= 2 &&
-        block_fixed + 24 * (4 * tree_bytes + (size_t)kRowNetScratchBytes) > kLdsCU) {
+        kLdsCU / (block_fixed + 4 * (4 * tree_bytes + (size_t)kRowNetScratchBytes)) < (size_t)reg_blocks) {
         const TreeLayout &full = prep[0]->tree;
         int32_t up = 0;
         for (int k = 1; k < full.levels; ++k) up += full.size[k];

@@ -12,6 +12,8 @@
   tree's lowest level in the state slot.
 * A batch holding an order-1.5e5 matrix (level 0 in the state slot) beside
   a small LDS-tier one.
+* The learned proposal in the four-per-wave kernel with a two-level tree,
+  level 0 in LDS (n = 5e4) and in the state slots (n = 8e4).
 
 Paths, alive flags, counters and path hashes compare bit for bit, ln X to
 1e-12 relative (the oracle's stated FP64 agreement)."""
@@ -46,6 +48,7 @@ def _check_sampled(M, sched, osch, seed, first, count, picks, model=None, alpha=
     out = est.run(first, count, seed, sched, want_hash=True, want_counters=True)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+    g["result"] = out["result"]
     est.close()
     A = O.OMatrix(M)
     pre = O.prep(A, osch)
@@ -71,6 +74,21 @@ def test_learned_headline_workload_benchmark_launch():
     model = R.quantize(R.init(31, scale=1.5))
     sched = P.preset("learned")
     _check_sampled(M, sched, _osched(sched, model, 0.01), 1, 0, 5000, [0, 2500, 4999], model=model)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n", [50_000, 80_000])
+def test_learned_rows_two_level_tree(n):
+    """Learned proposal in the four-per-wave kernel on a matrix whose
+    min-tree has two internal levels: at n = 5e4 four whole trees per wave
+    cost no resident blocks and level 0 stays in LDS; at n = 8e4 it moves to
+    the rows' state slots.  Sampled ids of one launch against the oracle."""
+    import paper_2608_15390_amd as P
+    M = G.planted_uniform(n, 7 * n, 41)
+    model = R.quantize(R.init(34, scale=1.5))
+    sched = P.preset("learned")
+    g = _check_sampled(M, sched, _osched(sched, model, 0.01), 5, 0, 600, [0, 299, 599], model=model)
+    assert g["result"]["launch_trajectories_per_wave"] == 4
 
 
 @pytest.mark.timeout(600)

@@ -140,14 +140,16 @@ struct RowTraj {
     // them).  Level 0 in the state slot is padded to whole 64-node blocks and
     // 256-byte aligned: one 16-byte load.
     __device__ void nodes4(int k, int32_t base, uint32_t (&w)[4]) const {
-        if (L0AS == kAsGlobal && k == 0) {
-            const uint4 q = *(const PE_G uint4 *)(lvl0 + base);
-            w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-        } else {
-            const int32_t last = a.tree.size[k] - 1;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) w[i] = node(k, base + i < last ? base + i : last);
+        if constexpr (L0AS == kAsGlobal) {
+            if (k == 0) {
+                const uint4 q = *reinterpret_cast<const PE_G uint4 *>(lvl0 + base);
+                w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+                return;
+            }
         }
+        const int32_t last = a.tree.size[k] - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = node(k, base + i < last ? base + i : last);
     }
     // The accessors below pick their array by a select rather than a branch:
     // lanes of one row may read rows and columns alike, and a load in each

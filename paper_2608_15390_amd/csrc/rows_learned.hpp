@@ -9,15 +9,18 @@
 // trajectory steps, and a wave keeps four trajectories' dependent memory
 // chains in flight instead of one.
 //
-// Per step of a row: selection down the row's min-tree (LDS) and the leaf
-// group; the candidates of v (one per lane for lists of up to 16 entries, a
+// Per step of a row: selection down the row's min-tree (upper levels in LDS,
+// the lowest in LDS or in the row's state slot), whose lowest level names
+// the vertex; the candidates of v (one per lane for lists of up to 16 entries, a
 // buffer in the state slot beyond that); the neighbourhood statistics of
 // every candidate from its flattened residual list (two 16-entry passes per
 // memory round trip, the first 32 entries kept in registers so that the
 // drawn candidate's list costs no second read); features written to the
 // wave's LDS record area; the tiles; logits read back; integer softmax,
 // uniform mix and the draw; removal and min-tree maintenance as in the
-// plain row kernel.
+// plain row kernel (v's leaf group, read at selection, for its refresh).
+// When every row is done, the last block to finish reduces the launch's
+// statistics.
 #pragma once
 #include "rows.hpp"
 
